@@ -1,0 +1,157 @@
+"""Python face of the CPU oracle (test infrastructure only).
+
+Wraps ``liboracle.so`` (plain C, see ``ace_oracle.c``) with numpy arrays.
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+may import this module.  Nothing here is shared with the GPU library.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+BC_HN, BC_HD, BC_P = 0, 1, 2
+BC_NAMES = {"HN": BC_HN, "HD": BC_HD, "P": BC_P}
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+_L = ctypes.POINTER(ctypes.c_long)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build
+            build.build()
+        L = ctypes.CDLL(LIB_PATH)
+        L.oracle_nodes_per_axis.argtypes = [ctypes.c_long, ctypes.c_int]
+        L.oracle_nodes_per_axis.restype = ctypes.c_long
+        L.oracle_node_coord.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_long]
+        L.oracle_node_coord.restype = ctypes.c_double
+        L.oracle_kappa.argtypes = [ctypes.c_double] * 3
+        L.oracle_kappa.restype = ctypes.c_double
+        L.oracle_root.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.oracle_root.restype = ctypes.c_double
+        L.oracle_root_array.argtypes = [ctypes.c_long, _D, ctypes.c_double, _D]
+        L.oracle_root_array.restype = None
+        L.oracle_xi.argtypes = [ctypes.c_int, _L, ctypes.c_int, ctypes.c_double, ctypes.c_double, _D, _D]
+        L.oracle_xi.restype = None
+        L.oracle_step.argtypes = [ctypes.c_int, _L, ctypes.c_int, ctypes.c_double, ctypes.c_double, _D, _D]
+        L.oracle_step.restype = None
+        L.oracle_bulk_sum.argtypes = [ctypes.c_long, _D]
+        L.oracle_bulk_sum.restype = ctypes.c_double
+        L.oracle_grad_sum.argtypes = [ctypes.c_int, _L, ctypes.c_int, _D]
+        L.oracle_grad_sum.restype = ctypes.c_double
+        L.oracle_energy.argtypes = [ctypes.c_int, _L, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D]
+        L.oracle_energy.restype = ctypes.c_double
+        L.oracle_maxnorm.argtypes = [ctypes.c_long, _D]
+        L.oracle_maxnorm.restype = ctypes.c_double
+        L.oracle_run.argtypes = [ctypes.c_int, _L, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, _D, ctypes.c_long, ctypes.c_long, _D, _D]
+        L.oracle_run.restype = ctypes.c_int
+        L.oracle_adjoint.argtypes = [ctypes.c_int, _L, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                     _D, ctypes.c_long, _D, _D, _D]
+        L.oracle_adjoint.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _bc(bc):
+    return BC_NAMES[bc] if isinstance(bc, str) else int(bc)
+
+
+def root(xi, h):
+    """Unique real root of theta + h(theta^3 - theta) = xi, elementwise."""
+    xi = _f64(np.atleast_1d(xi))
+    out = np.empty_like(xi)
+    lib().oracle_root_array(xi.size, _dp(xi), float(h), _dp(out))
+    return out
+
+
+class Problem:
+    """One Allen-Cahn problem: d, N[], L[], R[], eps, dt, bc (Sec. 2)."""
+
+    def __init__(self, d, N, L, R, eps, dt, bc):
+        self.d = int(d)
+        self.N = [int(n) for n in N][: self.d]
+        self.L = [float(x) for x in L][: self.d]
+        self.R = [float(x) for x in R][: self.d]
+        self.eps = float(eps)
+        self.dt = float(dt)
+        self.bc = _bc(bc)
+        self.h = 0.5 * self.dt
+        # Delta x = X / N (square mesh: all axes share one spacing)
+        self.dx = (self.R[0] - self.L[0]) / self.N[0]
+        self.kappa = lib().oracle_kappa(self.eps, self.dt, self.dx)
+        self.M = [int(lib().oracle_nodes_per_axis(n, self.bc)) for n in self.N]
+        self.shape = tuple(self.M)
+        self._Marr = (ctypes.c_long * 3)(*(self.M + [1] * (3 - self.d)))
+
+    # Theorem 2 hypothesis on the step: dt <= 1 - 2 d kappa, 0 < kappa < 1/(2d)
+    def conditions_ok(self, rel=1e-12):
+        return (self.dt <= (1.0 - 2 * self.d * self.kappa) * (1.0 + rel)
+                and 0.0 < self.kappa < 1.0 / (2 * self.d))
+
+    def coords(self, axis):
+        return np.array([lib().oracle_node_coord(self.bc, self.L[axis], self.dx, i)
+                         for i in range(self.M[axis])])
+
+    def xi(self, phi):
+        phi = _f64(phi).reshape(self.shape)
+        out = np.empty_like(phi)
+        lib().oracle_xi(self.d, self._Marr, self.bc, self.kappa, self.h, _dp(phi), _dp(out))
+        return out
+
+    def step(self, phi):
+        phi = _f64(phi).reshape(self.shape)
+        out = np.empty_like(phi)
+        lib().oracle_step(self.d, self._Marr, self.bc, self.kappa, self.h, _dp(phi), _dp(out))
+        return out
+
+    def run(self, phi0, nsteps, every=0):
+        """Returns (phi after nsteps, E series, max-norm series)."""
+        phi = _f64(phi0).reshape(self.shape).copy()
+        nmon = nsteps // every + 1 if every > 0 else 0
+        E = np.empty(max(nmon, 1))
+        mx = np.empty(max(nmon, 1))
+        rc = lib().oracle_run(self.d, self._Marr, self.bc, self.kappa, self.dt, self.dx,
+                              _dp(phi), int(nsteps), int(every), _dp(E), _dp(mx))
+        if rc != 0:
+            raise MemoryError("oracle_run")
+        return phi, E[:nmon], mx[:nmon]
+
+    def energy(self, phi):
+        phi = _f64(phi).reshape(self.shape)
+        return lib().oracle_energy(self.d, self._Marr, self.bc, self.kappa, self.dt, self.dx, _dp(phi))
+
+    def grad_sum(self, phi):
+        phi = _f64(phi).reshape(self.shape)
+        return lib().oracle_grad_sum(self.d, self._Marr, self.bc, _dp(phi))
+
+    def maxnorm(self, phi):
+        phi = _f64(phi)
+        return lib().oracle_maxnorm(phi.size, _dp(phi))
+
+    def adjoint(self, phi0, nsteps, lambdaT):
+        """(dL/dphi0, dL/dkappa, dL/d(eps^2)) for a given dL/dphi_T."""
+        phi0 = _f64(phi0).reshape(self.shape)
+        lam = _f64(lambdaT).reshape(self.shape)
+        g = np.empty_like(phi0)
+        gk = ctypes.c_double(0.0)
+        rc = lib().oracle_adjoint(self.d, self._Marr, self.bc, self.kappa, self.dt,
+                                  _dp(phi0), int(nsteps), _dp(lam), _dp(g), ctypes.byref(gk))
+        if rc != 0:
+            raise MemoryError("oracle_adjoint")
+        # kappa = eps^2 dt / dx^2, so dL/d(eps^2) = (dt / dx^2) dL/dkappa
+        return g, gk.value, gk.value * self.dt / (self.dx * self.dx)
