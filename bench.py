@@ -1,0 +1,189 @@
+"""Throughput benchmark of the RLB-MIE-FD Allen-Cahn step on one MI355X.
+
+Workload: 3D periodic, 512^3 nodes on (0,1)^3, eps = 0.02, dt = 5e-4
+(kappa = 0.0524288), a tanh sphere of radius 0.3 plus Uniform[-0.01, 0.01]
+noise clipped to [-1, 1], energy and max-norm fused every 100 steps.  One
+bench step is one time step of the scheme over the whole field; the field is
+resident in HBM before timing starts.
+
+Prints one JSON line: updates/s, the HBM roofline of the step kernel (16
+algorithmic bytes per node update: read phi^n, write phi^{n+1}), the CPU
+oracle timed on a bounded sample, and the adjoint cost ratio / batched
+speed-up of the other two workloads.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12            # MI355X HBM3E, bytes/s
+BYTES_PER_UPDATE = 16.0      # read phi^n + write phi^{n+1}
+MARCH_SRC = os.path.join(ROOT, "paper_2312_07010_amd", "csrc", "ace_march.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "march3d_p512_traffic.json")
+
+
+def _sha(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per step launch from the committed rocprofv3 counter runs,
+    if they were taken on the current marching-kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_src_sha") != _sha(MARCH_SRC):
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(w, phi0_full, sample_steps):
+    """The oracle as it stands, on a bounded sample of the same workload: the
+    full 512^3 field for `sample_steps` steps, all host threads."""
+    import oracle
+    p = oracle.Problem(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
+    t0 = time.perf_counter()
+    p.run(phi0_full, sample_steps)
+    t = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    upd = float(np.prod(p.shape)) * sample_steps
+    return {"value": upd / t, "unit": "grid-pt updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{'x'.join(map(str, p.shape))} field, {sample_steps} steps "
+                      f"({upd:.3g} updates, {t:.1f} s)"}
+
+
+def adjoint_ratio(ace, torch):
+    """Backward / forward wall time: 2D Neumann 512^2, 1000 steps, checkpoints
+    every 32 (forward = ace_forward_ckpt, backward = ace_backward)."""
+    from paper_2312_07010_amd import inputs
+    w = inputs.WADJ
+    s = ace.Solver(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
+    s.use_torch_stream()
+    phi0 = torch.tensor(inputs.uniform_field(s.shape, w.lo, w.hi, w.seed), device="cuda")
+    tgt = torch.tensor(inputs.uniform_field(s.shape, w.lo, w.hi, w.extra["target_seed"]),
+                       device="cuda")
+    s.forward_ckpt(phi0, 50, 32)
+    s.backward(torch.zeros_like(phi0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.forward_ckpt(phi0, w.steps, w.extra["ckpt_every"])
+    phiT = torch.empty_like(phi0)
+    s.get_phi(phiT)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g, _ = s.backward(phiT - tgt)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    s.close()
+    return (t2 - t1) / (t1 - t0), (t1 - t0) * 1e3, (t2 - t1) * 1e3
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--every", type=int, default=100)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the CPU baseline and the adjoint/batched side metrics")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2312_07010_amd import ace, inputs
+    assert torch.cuda.is_available(), "no GPU"
+    torch.cuda.set_device(0)
+
+    w = inputs.W3D
+    s = ace.Solver(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
+    s.use_torch_stream()
+    coords = [s.coords(a) for a in range(w.d)]
+    phi0 = inputs.initial_field(w, s.shape, coords)
+    phi0_dev = torch.tensor(phi0, device="cuda")
+    s.set_phi0(phi0_dev)
+    print(f"[bench] {w.name}: shape {s.shape}, params {s.params['kappa']:.7g} kappa, "
+          f"{s.params['newton_iters']} Newton steps", file=sys.stderr, flush=True)
+
+    # warmup (also JIT-loads every kernel variant used below)
+    s.run_monitored(args.warmup, args.every)
+    torch.cuda.synchronize()
+
+    s.set_phi0(phi0_dev)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    E, mx = s.run_monitored(args.steps, args.every)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    n = float(s.total)
+    updates = n * args.steps
+    value = updates / wall
+    print(f"[bench] {args.steps} steps in {wall:.3f} s wall, {gpu_ms:.1f} ms on the stream; "
+          f"max-norm {mx.max():.6f}, energy {E[0]:.6g} -> {E[-1]:.6g}", file=sys.stderr, flush=True)
+    if not (np.all(np.diff(E) <= 1e-14 * np.abs(E[:-1])) and mx.max() <= 1 + 4 * 2.0 ** -53):
+        print("[bench] WARNING: maximum principle or energy decay violated", file=sys.stderr)
+
+    # roofline of the step kernel: average launch time over the timed region
+    avg_launch_s = gpu_ms / 1e3 / args.steps
+    achieved = BYTES_PER_UPDATE * n / avg_launch_s
+    traffic = measured_traffic()
+    roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK, "traffic": traffic,
+            "kernel": "k_march3d (one step per launch)", "bytes_per_launch": BYTES_PER_UPDATE * n,
+            "avg_launch_us": avg_launch_s * 1e6}
+
+    out = {
+        "metric": "FP64 grid-pt updates/s + % HBM roofline; adjoint cost ratio; batched vs looped",
+        "value": value,
+        "unit": "grid-pt updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3D Allen-Cahn RLB-MIE-FD step, periodic, 512^3 nodes on (0,1)^3, "
+                               "eps 0.02, dt 5e-4, tanh sphere r 0.3 + U[-0.01,0.01] noise, "
+                               "energy + max-norm fused every 100 steps",
+                   "nodes": int(n), "monitor_every": args.every},
+        "roofline": roof,
+    }
+    s.close()
+    del phi0_dev
+    torch.cuda.empty_cache()
+
+    if not args.no_extras:
+        try:
+            ratio, fwd_ms, bwd_ms = adjoint_ratio(ace, torch)
+            out["adjoint_cost_ratio"] = ratio
+            out["adjoint_ms"] = {"forward": fwd_ms, "backward": bwd_ms}
+        except Exception as e:  # report, never hide
+            out["adjoint_cost_ratio"] = None
+            out["adjoint_error"] = repr(e)
+        out["batched_speedup"] = None
+        out["cpu_baseline"] = cpu_baseline(w, phi0, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

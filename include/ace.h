@@ -1,0 +1,259 @@
+/*
+ * ace.h - C ABI of the MI355X (gfx950) FP64 solver for the RLB-MIE-FD scheme
+ * of Chen, Liu, Chai and Shi (arXiv 2312.07010) for the d = 1, 2, 3
+ * Allen-Cahn equation  phi_t = eps^2 lap(phi) - (phi^3 - phi).
+ *
+ * All functions are extern "C", take plain host or device pointers and sizes,
+ * and return an int status: ACE_OK (0), a negative error (nothing changed
+ * unless stated), or a positive warning (the call completed).  Handles are not
+ * thread-safe; separate handles are independent.  Device pointers are HIP
+ * device memory on the device that was current when the handle was created.
+ *
+ * Notation: N = cells per axis, dx = (R - L)/N (equal on every axis),
+ * kappa = eps^2 dt / dx^2 (the paper's omega_1/s), h = dt/2,
+ * f(phi) = phi^3 - phi.  Fields are stored in C order (last index fastest),
+ * the paper's vector ordering (Sec. 2, vector form of the scheme).
+ */
+#ifndef ACE_H
+#define ACE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define ACE_OK 0
+#define ACE_E_ARG (-1)       /* bad argument (null, d, L >= R, eps <= 0, ...) */
+#define ACE_E_SIZE (-2)      /* too few cells for the boundary condition      */
+#define ACE_E_ANISO (-3)     /* dx differs between axes                        */
+#define ACE_E_DT (-4)        /* dt <= 0 or dt >= 2: the cubic has no unique root */
+#define ACE_E_HIP (-5)       /* a HIP runtime call failed                      */
+#define ACE_E_NOMEM (-6)     /* device or host allocation failed               */
+#define ACE_E_NONFINITE (-7) /* NaN or Inf in a field                          */
+#define ACE_E_STATE (-8)     /* call not valid in the handle's current state   */
+#define ACE_W_CONDITIONS 1   /* dt > 1 - 2 d kappa or kappa >= 1/(2d): Theorem 2's
+                                step condition fails (the run is still allowed) */
+#define ACE_W_PHI0_GT1 2     /* |phi0| > 1 somewhere: Theorem 2's hypothesis fails */
+#define ACE_W_MAXPRINCIPLE 3 /* a monitored max-norm exceeded 1 + 4 u while the
+                                conditions hold                                 */
+#define ACE_W_ENERGY_UP 4    /* a monitored energy rose by more than 1e-14 E
+                                while the conditions hold                       */
+
+/* ---- boundary conditions (Sec. 1; D matrices of Sec. 2) ----------------- */
+#define ACE_BC_HN 0 /* homogeneous Neumann: N+2 nodes at L + (i - 1/2) dx     */
+#define ACE_BC_HD 1 /* homogeneous Dirichlet: N-1 nodes at L + i dx, i=1..N-1 */
+#define ACE_BC_P 2  /* periodic: N nodes at L + i dx, i = 0..N-1               */
+
+/* ---- where a pointer lives --------------------------------------------- */
+#define ACE_HOST 0
+#define ACE_DEVICE 1
+
+/* ---- kernel selection (ace_set_kernel) --------------------------------- */
+#define ACE_KERNEL_AUTO 0    /* the autotuned / default choice                */
+#define ACE_KERNEL_DIRECT 1  /* one thread per node, neighbours from cache    */
+#define ACE_KERNEL_MARCH 2   /* 2D/3D: tiles marching along axis 0, LDS planes */
+#define ACE_KERNEL_RESIDENT 3 /* whole field in LDS, many steps per launch    */
+#define ACE_KERNEL_TBLOCK 4  /* 2D/3D: temporal blocking, `depth` steps/launch */
+
+typedef struct ace_solver ace_solver;
+
+/* Derived parameters of a handle (Sec. 2 and Theorem 2 of Sec. 3.2). */
+typedef struct {
+    int d;              /* dimension 1..3                                    */
+    int bc;             /* ACE_BC_*                                          */
+    int64_t N[3];       /* cells per axis (unused axes 1)                    */
+    int64_t M[3];       /* stored nodes per axis (unused axes 1)             */
+    int64_t total;      /* product of M                                      */
+    double dx, dt, eps; /* spacing, time step, interface width              */
+    double kappa;       /* eps^2 dt / dx^2                                   */
+    double h;           /* dt / 2                                            */
+    double dt_bound;    /* largest dt with dt <= 1 - 2 d eps^2 dt/dx^2:
+                           dx^2 / (dx^2 + 2 d eps^2)                          */
+    double omega1;      /* the paper's weight choice 1/3, 1/5, 1/6 (Sec. 4)  */
+    double s;           /* relaxation parameter omega1 / kappa              */
+    int conditions_ok;  /* 1 if dt <= (1 - 2 d kappa)(1 + 1e-12) and
+                           0 < kappa < 1/(2d)                                 */
+    int newton_iters;   /* Newton steps of the pointwise cubic solve         */
+} ace_params_t;
+
+/* ---- handle lifecycle --------------------------------------------------- */
+
+/* Creates a solver for the problem of Sec. 1 on Omega = prod (L[j], R[j])
+ * with N[j] cells per axis, interface width eps > 0, time step 0 < dt < 2 and
+ * one boundary condition bc for the whole boundary.  Allocates two device
+ * field buffers (C order, ace_shape nodes) and monitor scratch on the current
+ * device and stream 0.  *out receives the handle (free with ace_destroy).
+ * Errors: ACE_E_ARG (null pointers, d not 1..3, L >= R, eps <= 0, non-finite
+ * input, bc unknown), ACE_E_SIZE (HN N < 1, HD N < 2, P N < 3),
+ * ACE_E_ANISO (dx differs across axes by more than 1e-12 relative),
+ * ACE_E_DT, ACE_E_HIP / ACE_E_NOMEM.  Warning: ACE_W_CONDITIONS. */
+int ace_create(int d, const int64_t *N, const double *L, const double *R,
+               double eps, double dt, int bc, ace_solver **out);
+
+/* Frees the handle and the device memory it owns (not bound buffers). */
+int ace_destroy(ace_solver *s);
+
+/* Stored nodes per axis M[0..2] (unused axes 1) and their product. */
+int ace_shape(const ace_solver *s, int64_t M[3], int64_t *total);
+
+/* Coordinates of the stored nodes along axis (Sec. 2, grid function space):
+ * x must hold M[axis] doubles (host). */
+int ace_node_coords(const ace_solver *s, int axis, double *x);
+
+/* Copies the derived parameters to *p (host). */
+int ace_params(const ace_solver *s, ace_params_t *p);
+
+/* Runs all later device work of the handle on this HIP stream (hipStream_t,
+ * may be NULL for the default stream). */
+int ace_set_stream(ace_solver *s, void *hip_stream);
+
+/* Uses caller-owned device buffers a, b (each ace_shape total doubles) as
+ * the two field buffers from now on; the handle never frees them.  The
+ * current field is lost: call ace_set_phi0 next.  Both NULL reverts to the
+ * handle's own buffers. */
+int ace_bind_fields(ace_solver *s, double *a, double *b);
+
+/* Kernel choice for ace_step (ACE_KERNEL_*) and its temporal depth (steps
+ * per launch; 0 = default).  Every choice computes the same result. */
+int ace_set_kernel(ace_solver *s, int kernel, int depth);
+
+/* ---- the time step (Sec. 2, scheme IE-FD; Sec. 3.2, Remark 1) ------------ */
+
+/* Sets phi^0 from total doubles in C order at phi0 (ACE_HOST: synchronous
+ * copy; ACE_DEVICE: stream-ordered copy) and resets the step counter.
+ * Errors: ACE_E_NONFINITE (host copies are checked).  Warning:
+ * ACE_W_PHI0_GT1 (host copies). */
+int ace_set_phi0(ace_solver *s, const double *phi0, int where);
+
+/* Advances the field by nsteps >= 0 steps of
+ *   phi^{n+1} + h f(phi^{n+1}) = phi^n + kappa sum_k (phi_{+k} + phi_{-k}
+ *                                 - 2 phi) - h f(phi^n),
+ * solving the monotone cubic for its unique real root per node.  Out-of-range
+ * neighbours: HN mirror (the node itself), HD zero, P wrap.  Asynchronous on
+ * the handle's stream. */
+int ace_step(ace_solver *s, int64_t nsteps);
+
+/* Advances by nsteps and records the discrete energy (Theorem 3) and the
+ * max-norm at steps 0, every, 2 every, ... <= nsteps into host arrays E and
+ * maxn of length nsteps/every + 1 (every >= 1).  The monitors of the field
+ * a step reads are fused into that step.  Synchronous.  Errors:
+ * ACE_E_NONFINITE.  Warnings (conditions_ok only): ACE_W_MAXPRINCIPLE,
+ * ACE_W_ENERGY_UP. */
+int ace_run_monitored(ace_solver *s, int64_t nsteps, int64_t every,
+                      double *E, double *maxn);
+
+/* Discrete energy of the current field (Sec. 3.3, Theorem 3):
+ *   E = dx^d [ sum_i (phi_i^2 - 1)^2 / 4 - kappa/(2 dt) Phi^T Lambda Phi ],
+ * with -Phi^T Lambda Phi the sum of squared differences over lattice edges
+ * (HD includes the edges to the zero walls, P the wrap edges).  Deterministic
+ * fixed-order reduction.  Synchronous; *E is host memory. */
+int ace_energy(ace_solver *s, double *E);
+
+/* max_i |phi_i| of the current field (Sec. 3.2, Theorem 2).  NaN if any node
+ * is NaN.  Synchronous; *m is host memory. */
+int ace_maxnorm(ace_solver *s, double *m);
+
+/* Copies the current field (total doubles, C order) to out. */
+int ace_get_phi(ace_solver *s, double *out, int where);
+
+/* Steps taken since the last ace_set_phi0. */
+int64_t ace_step_count(const ace_solver *s);
+
+/* Device pointer of the current field (valid until the next step). */
+const double *ace_field_ptr(const ace_solver *s);
+
+const char *ace_strerror(int status);
+
+/* ---- reverse mode (adjoint of the time loop) ---------------------------- */
+
+/* Gradient of a loss L(phi^T) through nsteps steps from phi0, given
+ * lambdaT = dL/dphi^T.  Each step is phi^{n+1} = R(xi(phi^n)) with R the
+ * root of the cubic, so the transposed step is
+ *   mu      = lambda^{n+1} / (1 + h (3 (phi^{n+1})^2 - 1)),
+ *   lambda^n = (1 - h (3 (phi^n)^2 - 1)) mu + kappa Lambda mu
+ * (Lambda is symmetric: the D matrices of Sec. 2 are), and
+ *   dL/dkappa = sum_n < mu, Lambda phi^n >.
+ * Forward states are checkpointed every ckpt_every steps (>= 1) on the
+ * device and each segment is recomputed during the reverse sweep.
+ * Outputs: dphi0 (total doubles) and *deps2 = (dt/dx^2) dL/dkappa
+ * (host double).  phi0, lambdaT and dphi0 live where `where` says.  The
+ * handle's field afterwards holds phi^T.  Errors: ACE_E_NOMEM, ACE_E_ARG. */
+int ace_adjoint(ace_solver *s, const double *phi0, int64_t nsteps,
+                int64_t ckpt_every, const double *lambdaT, double *dphi0,
+                double *deps2, int where);
+
+/* The two halves of ace_adjoint, for callers that need phi^T before they can
+ * form lambdaT (e.g. an autograd forward/backward pair).
+ * ace_forward_ckpt sets phi^0 (where: ACE_HOST or ACE_DEVICE), advances
+ * nsteps and keeps every ckpt_every-th state (steps 0, k, 2k, ...) in device
+ * memory owned by the handle; the field then holds phi^T.
+ * ace_backward consumes those checkpoints: given lambdaT = dL/dphi^T it
+ * recomputes each segment and runs the transposed steps in reverse, writing
+ * dphi0 and *deps2 (host).  Errors: ACE_E_STATE if no checkpoints exist or
+ * the field was changed since ace_forward_ckpt. */
+int ace_forward_ckpt(ace_solver *s, const double *phi0, int where, int64_t nsteps,
+                     int64_t ckpt_every);
+int ace_backward(ace_solver *s, const double *lambdaT, double *dphi0, double *deps2,
+                 int where);
+
+/* ---- batches of independent instances ----------------------------------- */
+
+typedef struct ace_batch ace_batch;
+
+/* One instance of a batch: the ace_create arguments. */
+typedef struct {
+    int d;
+    int bc;
+    int64_t N[3];
+    double L[3];
+    double R[3];
+    double eps;
+    double dt;
+} ace_instance_desc;
+
+/* Creates a batch of count instances (each validated as ace_create does;
+ * status[i] receives each instance's status when status is not NULL).
+ * Allocates one device arena for all fields.  Instances of one batch run in
+ * one persistent launch: workgroups take (instance, tile) tasks from a queue
+ * ordered by decreasing cost. */
+int ace_batch_create(int count, const ace_instance_desc *desc,
+                     ace_batch **out, int *status);
+int ace_batch_destroy(ace_batch *b);
+/* Stored nodes of instance i (M[0..2]) and its offset in doubles into the
+ * arena (for device-side initialisation). */
+int ace_batch_shape(const ace_batch *b, int i, int64_t M[3], int64_t *total,
+                    int64_t *offset);
+int ace_batch_set_stream(ace_batch *b, void *hip_stream);
+/* Sets phi^0 of instance i (host or device pointer). */
+int ace_batch_set_phi0(ace_batch *b, int i, const double *phi0, int where);
+/* Sets every instance's phi^0 from one host array holding all instances
+ * back to back in instance order (sum of totals doubles). */
+int ace_batch_set_all(ace_batch *b, const double *phi0_all, int where);
+/* Advances every instance by nsteps in one persistent launch. */
+int ace_batch_step(ace_batch *b, int64_t nsteps);
+/* Energy and max-norm of every instance (host arrays of count doubles). */
+int ace_batch_monitor(ace_batch *b, double *E, double *maxn);
+int ace_batch_get_phi(ace_batch *b, int i, double *out, int where);
+int ace_batch_get_all(ace_batch *b, double *out_all, int where);
+
+/* ---- autotuner ------------------------------------------------------------ */
+
+/* Times each kernel choice (and temporal depth) on the handle's problem for
+ * trial_steps steps from the current field, keeps the fastest as the
+ * ACE_KERNEL_AUTO choice, restores the field, and writes a one-line JSON
+ * record of the timings into json (capacity cap bytes, may be NULL).  If the
+ * environment variable ACE_AUTOTUNE_CACHE names a file, the choice is
+ * appended there and later handles of the same (d, bc, shape) reuse it. */
+int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap);
+
+/* Library version string. */
+const char *ace_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACE_H */

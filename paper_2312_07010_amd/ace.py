@@ -1,0 +1,290 @@
+"""Python binding of libace.so (the C ABI in include/ace.h).
+
+Argument marshalling only: every step of the solver runs in the HIP kernels
+of the library.  Host arrays are numpy float64 in C order; device arrays are
+torch tensors on the GPU (float64, contiguous), passed by pointer together
+with torch's current HIP stream.  There is no CPU fallback: if the library
+is missing, loading fails with an error.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libace.so")
+
+ACE_OK = 0
+ACE_E_ARG, ACE_E_SIZE, ACE_E_ANISO, ACE_E_DT = -1, -2, -3, -4
+ACE_E_HIP, ACE_E_NOMEM, ACE_E_NONFINITE, ACE_E_STATE = -5, -6, -7, -8
+ACE_W_CONDITIONS, ACE_W_PHI0_GT1, ACE_W_MAXPRINCIPLE, ACE_W_ENERGY_UP = 1, 2, 3, 4
+ACE_BC_HN, ACE_BC_HD, ACE_BC_P = 0, 1, 2
+BC = {"HN": ACE_BC_HN, "HD": ACE_BC_HD, "P": ACE_BC_P}
+ACE_HOST, ACE_DEVICE = 0, 1
+ACE_KERNEL_AUTO, ACE_KERNEL_DIRECT, ACE_KERNEL_MARCH = 0, 1, 2
+ACE_KERNEL_RESIDENT, ACE_KERNEL_TBLOCK = 3, 4
+
+_i64 = ctypes.c_int64
+_dbl = ctypes.c_double
+_vp = ctypes.c_void_p
+_P = ctypes.POINTER
+
+
+class AceError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("bc", ctypes.c_int), ("N", _i64 * 3), ("M", _i64 * 3),
+                ("total", _i64), ("dx", _dbl), ("dt", _dbl), ("eps", _dbl), ("kappa", _dbl),
+                ("h", _dbl), ("dt_bound", _dbl), ("omega1", _dbl), ("s", _dbl),
+                ("conditions_ok", ctypes.c_int), ("newton_iters", ctypes.c_int)]
+
+    def as_dict(self):
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if hasattr(v, "__len__") else v
+        return out
+
+
+class InstanceDesc(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("bc", ctypes.c_int), ("N", _i64 * 3), ("L", _dbl * 3),
+                ("R", _dbl * 3), ("eps", _dbl), ("dt", _dbl)]
+
+
+_SIGS = {
+    "ace_version": (ctypes.c_char_p, []),
+    "ace_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "ace_create": (ctypes.c_int, [ctypes.c_int, _P(_i64), _P(_dbl), _P(_dbl), _dbl, _dbl,
+                                  ctypes.c_int, _P(_vp)]),
+    "ace_destroy": (ctypes.c_int, [_vp]),
+    "ace_shape": (ctypes.c_int, [_vp, _P(_i64), _P(_i64)]),
+    "ace_node_coords": (ctypes.c_int, [_vp, ctypes.c_int, _P(_dbl)]),
+    "ace_params": (ctypes.c_int, [_vp, _P(Params)]),
+    "ace_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "ace_bind_fields": (ctypes.c_int, [_vp, _vp, _vp]),
+    "ace_set_kernel": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    "ace_set_phi0": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "ace_step": (ctypes.c_int, [_vp, _i64]),
+    "ace_run_monitored": (ctypes.c_int, [_vp, _i64, _i64, _P(_dbl), _P(_dbl)]),
+    "ace_energy": (ctypes.c_int, [_vp, _P(_dbl)]),
+    "ace_maxnorm": (ctypes.c_int, [_vp, _P(_dbl)]),
+    "ace_get_phi": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "ace_step_count": (_i64, [_vp]),
+    "ace_field_ptr": (_vp, [_vp]),
+    "ace_adjoint": (ctypes.c_int, [_vp, _vp, _i64, _i64, _vp, _vp, _P(_dbl), ctypes.c_int]),
+    "ace_forward_ckpt": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _i64, _i64]),
+    "ace_backward": (ctypes.c_int, [_vp, _vp, _vp, _P(_dbl), ctypes.c_int]),
+    "ace_batch_create": (ctypes.c_int, [ctypes.c_int, _P(InstanceDesc), _P(_vp), _P(ctypes.c_int)]),
+    "ace_batch_destroy": (ctypes.c_int, [_vp]),
+    "ace_batch_shape": (ctypes.c_int, [_vp, ctypes.c_int, _P(_i64), _P(_i64), _P(_i64)]),
+    "ace_batch_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "ace_batch_set_phi0": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int]),
+    "ace_batch_set_all": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "ace_batch_step": (ctypes.c_int, [_vp, _i64]),
+    "ace_batch_monitor": (ctypes.c_int, [_vp, _P(_dbl), _P(_dbl)]),
+    "ace_batch_get_phi": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int]),
+    "ace_batch_get_all": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "ace_autotune": (ctypes.c_int, [_vp, _i64, ctypes.c_char_p, ctypes.c_size_t]),
+}
+
+_lib = None
+
+
+def lib():
+    """Loads libace.so once; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2312_07010_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(code):
+    return lib().ace_strerror(int(code)).decode()
+
+
+def _check(code, where):
+    if code < 0:
+        raise AceError(code, where)
+    return code
+
+
+def _host(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data
+
+
+def _is_device(x):
+    return hasattr(x, "is_cuda") and x.is_cuda
+
+
+def _dev(t):
+    import torch
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("device arrays must be contiguous float64 tensors")
+    return t.data_ptr()
+
+
+def current_stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Solver:
+    """One problem of the paper (Sec. 1): d, N[], L[], R[], eps, dt, bc."""
+
+    def __init__(self, d, N, L, R, eps, dt, bc):
+        bc = BC[bc] if isinstance(bc, str) else int(bc)
+        n = (_i64 * 3)(*[int(v) for v in list(N) + [1] * (3 - len(N))])
+        lo = (_dbl * 3)(*[float(v) for v in list(L) + [0.0] * (3 - len(L))])
+        hi = (_dbl * 3)(*[float(v) for v in list(R) + [1.0] * (3 - len(R))])
+        h = _vp()
+        self.status = _check(lib().ace_create(int(d), n, lo, hi, float(eps), float(dt), bc,
+                                              ctypes.byref(h)), "ace_create")
+        self._h = h
+        M = (_i64 * 3)()
+        tot = _i64()
+        _check(lib().ace_shape(h, M, ctypes.byref(tot)), "ace_shape")
+        self.d = int(d)
+        self.shape = tuple(int(M[j]) for j in range(self.d))
+        self.total = int(tot.value)
+        self.last_status = self.status
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ace_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def params(self):
+        p = Params()
+        _check(lib().ace_params(self._h, ctypes.byref(p)), "ace_params")
+        return p.as_dict()
+
+    def coords(self, axis):
+        x = np.empty(self.shape[axis])
+        _check(lib().ace_node_coords(self._h, int(axis), x.ctypes.data_as(_P(_dbl))), "ace_node_coords")
+        return x
+
+    def set_stream(self, stream):
+        _check(lib().ace_set_stream(self._h, stream), "ace_set_stream")
+
+    def use_torch_stream(self):
+        self.set_stream(current_stream())
+
+    def bind_fields(self, a, b):
+        pa = _dev(a) if a is not None else None
+        pb = _dev(b) if b is not None else None
+        _check(lib().ace_bind_fields(self._h, pa, pb), "ace_bind_fields")
+
+    def set_kernel(self, kernel, depth=0):
+        _check(lib().ace_set_kernel(self._h, int(kernel), int(depth)), "ace_set_kernel")
+
+    def set_phi0(self, phi0):
+        if _is_device(phi0):
+            rc = lib().ace_set_phi0(self._h, _dev(phi0), ACE_DEVICE)
+        else:
+            a, p = _host(phi0)
+            if a.size != self.total:
+                raise ValueError("phi0 has the wrong size")
+            rc = lib().ace_set_phi0(self._h, p, ACE_HOST)
+        self.last_status = _check(rc, "ace_set_phi0")
+        return self.last_status
+
+    def step(self, nsteps):
+        self.last_status = _check(lib().ace_step(self._h, int(nsteps)), "ace_step")
+        return self.last_status
+
+    def run_monitored(self, nsteps, every):
+        n = int(nsteps) // int(every) + 1
+        E = np.empty(n)
+        mx = np.empty(n)
+        rc = lib().ace_run_monitored(self._h, int(nsteps), int(every), E.ctypes.data_as(_P(_dbl)),
+                                     mx.ctypes.data_as(_P(_dbl)))
+        self.last_status = _check(rc, "ace_run_monitored")
+        return E, mx
+
+    def energy(self):
+        v = _dbl()
+        _check(lib().ace_energy(self._h, ctypes.byref(v)), "ace_energy")
+        return v.value
+
+    def maxnorm(self):
+        v = _dbl()
+        _check(lib().ace_maxnorm(self._h, ctypes.byref(v)), "ace_maxnorm")
+        return v.value
+
+    def get_phi(self, out=None):
+        if out is not None and _is_device(out):
+            _check(lib().ace_get_phi(self._h, _dev(out), ACE_DEVICE), "ace_get_phi")
+            return out
+        a = np.empty(self.shape)
+        _check(lib().ace_get_phi(self._h, a.ctypes.data, ACE_HOST), "ace_get_phi")
+        return a
+
+    @property
+    def step_count(self):
+        return int(lib().ace_step_count(self._h))
+
+    def field_ptr(self):
+        return lib().ace_field_ptr(self._h)
+
+    # reverse mode ---------------------------------------------------------
+    def forward_ckpt(self, phi0, nsteps, ckpt_every):
+        if _is_device(phi0):
+            rc = lib().ace_forward_ckpt(self._h, _dev(phi0), ACE_DEVICE, int(nsteps), int(ckpt_every))
+        else:
+            a, p = _host(phi0)
+            rc = lib().ace_forward_ckpt(self._h, p, ACE_HOST, int(nsteps), int(ckpt_every))
+        return _check(rc, "ace_forward_ckpt")
+
+    def backward(self, lambdaT, dphi0=None):
+        g = _dbl()
+        if _is_device(lambdaT):
+            import torch
+            out = dphi0 if dphi0 is not None else torch.empty_like(lambdaT)
+            rc = lib().ace_backward(self._h, _dev(lambdaT), _dev(out), ctypes.byref(g), ACE_DEVICE)
+        else:
+            lam, p = _host(lambdaT)
+            out = np.empty(self.shape)
+            rc = lib().ace_backward(self._h, p, out.ctypes.data, ctypes.byref(g), ACE_HOST)
+        _check(rc, "ace_backward")
+        return out, g.value
+
+    def adjoint(self, phi0, nsteps, ckpt_every, lambdaT):
+        """Host arrays in, (dL/dphi0, dL/d(eps^2)) out."""
+        a, pa = _host(phi0)
+        lam, pl = _host(lambdaT)
+        out = np.empty(self.shape)
+        g = _dbl()
+        rc = lib().ace_adjoint(self._h, pa, int(nsteps), int(ckpt_every), pl, out.ctypes.data,
+                               ctypes.byref(g), ACE_HOST)
+        _check(rc, "ace_adjoint")
+        return out, g.value
+
+    def autotune(self, trial_steps=20):
+        buf = ctypes.create_string_buffer(4096)
+        _check(lib().ace_autotune(self._h, int(trial_steps), buf, 4096), "ace_autotune")
+        return buf.value.decode()

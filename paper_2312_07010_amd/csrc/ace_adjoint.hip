@@ -1,0 +1,139 @@
+// Transposed step of the scheme (reverse sweep of the time loop).
+//
+// Forward: phi^{n+1}_i = R(xi_i), xi = phi + kappa Lambda phi - h f(phi), with R
+// the root of theta + h (theta^3 - theta) = xi.  Implicit differentiation of
+// the cubic gives R'(xi) = 1 / (1 + h (3 theta^2 - 1)).  The Jacobian of xi is
+// diag(1 - h (3 phi^2 - 1)) + kappa Lambda and Lambda is symmetric (the D
+// matrices of Sec. 2 are), so with mu = lambda^{n+1} R'(xi):
+//   lambda^n = (1 - h (3 (phi^n)^2 - 1)) mu + kappa Lambda mu,
+//   dL/dkappa += < mu, Lambda phi^n >.
+// mu at the neighbours is recomputed from lambda^{n+1} and phi^{n+1} instead
+// of being stored, so one pass reads three fields and writes one.
+#include "ace_device.h"
+
+namespace ace {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ double mu_of(double lam, double p1, const StepCoef &c)
+{
+    // 1 + h (3 p1^2 - 1) = (1 - h) + 3 h p1^2
+    return lam / fma(c.h3, p1 * p1, c.omh);
+}
+
+template <int D, int BC>
+__global__ __launch_bounds__(kBlock) void k_adjoint(Shape s, StepCoef c,
+                                                    const double *__restrict__ lam,
+                                                    const double *__restrict__ phin,
+                                                    const double *__restrict__ phin1,
+                                                    double *__restrict__ lam_out,
+                                                    double *__restrict__ gpart)
+{
+    __shared__ double lds[kBlock / 64];
+    const int64_t i2 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i1 = (int64_t)blockIdx.y * blockDim.y + threadIdx.y;
+    const int64_t i0 = blockIdx.z;
+    double g = 0.0;
+    if (i2 < s.M2 && i1 < s.M1) {
+        const int64_t idx = (i0 * s.M1 + i1) * s.M2 + i2;
+        const double mu = mu_of(lam[idx], phin1[idx], c);
+        const double p = phin[idx];
+        const int64_t coord[3] = {i0, i1, i2};
+        const int64_t size[3] = {s.M0, s.M1, s.M2};
+        const int64_t stride[3] = {s.M1 * s.M2, s.M2, 1};
+        double msum = 0.0, psum = 0.0;
+#pragma unroll
+        for (int a = 3 - D; a < 3; ++a) {
+            const int64_t cc = coord[a], n = size[a], st = stride[a];
+            double mlo, mhi, plo, phi;
+            if (cc > 0) {
+                mlo = mu_of(lam[idx - st], phin1[idx - st], c);
+                plo = phin[idx - st];
+            } else if (BC == BC_HN) {
+                mlo = mu;
+                plo = p;
+            } else if (BC == BC_HD) {
+                mlo = 0.0;
+                plo = 0.0;
+            } else {
+                const int64_t w = idx + (n - 1) * st;
+                mlo = mu_of(lam[w], phin1[w], c);
+                plo = phin[w];
+            }
+            if (cc < n - 1) {
+                mhi = mu_of(lam[idx + st], phin1[idx + st], c);
+                phi = phin[idx + st];
+            } else if (BC == BC_HN) {
+                mhi = mu;
+                phi = p;
+            } else if (BC == BC_HD) {
+                mhi = 0.0;
+                phi = 0.0;
+            } else {
+                const int64_t w = idx - (n - 1) * st;
+                mhi = mu_of(lam[w], phin1[w], c);
+                phi = phin[w];
+            }
+            msum += mlo + mhi;
+            psum += plo + phi;
+        }
+        const double lap_mu = fma(-2.0 * D, mu, msum);
+        const double lap_p = fma(-2.0 * D, p, psum);
+        // 1 - h (3 p^2 - 1) = (1 + h) - 3 h p^2
+        const double jd = fma(-c.h3, p * p, 1.0 + c.h);
+        lam_out[idx] = fma(c.kappa, lap_mu, jd * mu);
+        g = mu * lap_p;
+    }
+    g = wave_sum(g);
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    if ((tid & 63) == 0) lds[tid >> 6] = g;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) t += lds[w];
+        gpart[blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z)] = t;
+    }
+}
+
+void adj_grid(const Shape &s, dim3 &grid, dim3 &block)
+{
+    int bx = 1;
+    while (bx < s.M2 && bx < kBlock) bx <<= 1;
+    if (s.d == 1) bx = kBlock;
+    const int by = kBlock / bx;
+    block = dim3(bx, by, 1);
+    grid = dim3((unsigned)((s.M2 + bx - 1) / bx), (unsigned)((s.M1 + by - 1) / by), (unsigned)s.M0);
+}
+
+}  // namespace
+
+int64_t adjoint_partials_needed(const Shape &s)
+{
+    dim3 grid, block;
+    adj_grid(s, grid, block);
+    return (int64_t)grid.x * grid.y * grid.z;
+}
+
+hipError_t launch_adjoint_step(const Shape &s, const StepCoef &c, const double *lam,
+                               const double *phin, const double *phin1, double *lam_out,
+                               double *gpart, int64_t *nparts, hipStream_t st)
+{
+    dim3 grid, block;
+    adj_grid(s, grid, block);
+    if (nparts) *nparts = (int64_t)grid.x * grid.y * grid.z;
+#define ACE_ADJ(DD, BB)                                                                        \
+    if (s.d == DD && s.bc == BB) {                                                             \
+        hipLaunchKernelGGL((k_adjoint<DD, BB>), grid, block, 0, st, s, c, lam, phin, phin1,    \
+                           lam_out, gpart);                                                    \
+        return hipGetLastError();                                                              \
+    }
+    ACE_ADJ(1, BC_HN) ACE_ADJ(1, BC_HD) ACE_ADJ(1, BC_P)
+    ACE_ADJ(2, BC_HN) ACE_ADJ(2, BC_HD) ACE_ADJ(2, BC_P)
+    ACE_ADJ(3, BC_HN) ACE_ADJ(3, BC_HD) ACE_ADJ(3, BC_P)
+#undef ACE_ADJ
+    return hipErrorInvalidValue;
+}
+
+}  // namespace ace

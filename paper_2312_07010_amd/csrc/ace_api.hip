@@ -1,0 +1,630 @@
+// Host runtime behind the C ABI declared in include/ace.h: argument checks,
+// derived parameters (Sec. 2; Theorem 2 of Sec. 3.2), device buffers, kernel
+// dispatch, monitored runs, and the checkpointed reverse sweep.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/ace.h"
+#include "ace_internal.h"
+#include "ace_runtime.h"
+
+using namespace ace;
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+namespace ace {
+
+int hip_status(hipError_t e)
+{
+    if (e == hipSuccess) return ACE_OK;
+    if (e == hipErrorOutOfMemory) return ACE_E_NOMEM;
+    if (getenv("ACE_LOG")) fprintf(stderr, "[ace] HIP error: %s\n", hipGetErrorString(e));
+    return ACE_E_HIP;
+}
+
+int64_t nodes_per_axis(int64_t N, int bc)
+{
+    if (bc == ACE_BC_HN) return N + 2;
+    if (bc == ACE_BC_HD) return N - 1;
+    return N;
+}
+
+// Newton steps from theta_0 = |xi| that bring the relative error of the root
+// below 2^-54 for every |xi| <= 1.  With q = 3h/(1-h) the error obeys
+// r_{k+1} <= q (1 + r_k) r_k^2 (p'' = 6 h theta <= 6h, p' >= 1 - h), starting
+// from r_0 <= h/(1-h) (the root lies in [|xi|, |xi|/(1-h)]).  One extra step
+// covers the rounding of the reciprocal and of the residual.
+int newton_iters_for(double h)
+{
+    const double q = 3.0 * h / (1.0 - h);
+    double r = h / (1.0 - h);
+    int k = 0;
+    while (r > 0x1p-54 && k < 60) {
+        r = q * (1.0 + r) * r * r + 0x1p-46 * r;
+        ++k;
+    }
+    return k + 1 > 2 ? k + 1 : 2;
+}
+
+// Validates the ace_create arguments and fills the derived parameters.
+int derive(int d, const int64_t *N, const double *L, const double *R, double eps, double dt,
+           int bc, Problem &p)
+{
+    if (!N || !L || !R) return ACE_E_ARG;
+    if (d < 1 || d > 3) return ACE_E_ARG;
+    if (bc != ACE_BC_HN && bc != ACE_BC_HD && bc != ACE_BC_P) return ACE_E_ARG;
+    if (!(eps > 0.0) || !isfinite(eps)) return ACE_E_ARG;
+    if (!isfinite(dt)) return ACE_E_ARG;
+    const int64_t minN = (bc == ACE_BC_HN) ? 1 : (bc == ACE_BC_HD ? 2 : 3);
+    memset(&p, 0, sizeof(p));
+    p.d = d;
+    p.bc = bc;
+    for (int j = 0; j < 3; ++j) {
+        p.N[j] = 1;
+        p.M[j] = 1;
+        p.L[j] = 0.0;
+        p.R[j] = 1.0;
+    }
+    double dx0 = 0.0;
+    for (int j = 0; j < d; ++j) {
+        if (!isfinite(L[j]) || !isfinite(R[j]) || !(L[j] < R[j])) return ACE_E_ARG;
+        if (N[j] < minN) return ACE_E_SIZE;
+        if (N[j] > (int64_t)1 << 31) return ACE_E_SIZE;
+        const double dx = (R[j] - L[j]) / (double)N[j];
+        if (j == 0) dx0 = dx;
+        else if (fabs(dx - dx0) > 1e-12 * dx0) return ACE_E_ANISO;
+        p.N[j] = N[j];
+        p.L[j] = L[j];
+        p.R[j] = R[j];
+    }
+    if (!(dt > 0.0) || !(dt < 2.0)) return ACE_E_DT;
+    p.dx = dx0;
+    p.dt = dt;
+    p.eps = eps;
+    // kappa = eps^2 dt / dx^2 (Sec. 2: eps^2 = (omega_1/s) dx^2 / dt)
+    p.kappa = eps * eps * dt / (dx0 * dx0);
+    p.h = 0.5 * dt;
+    // stored nodes: fastest axis last; a d-dimensional field occupies the
+    // last d of the three internal axes
+    int64_t total = 1;
+    for (int j = 0; j < d; ++j) {
+        const int64_t m = nodes_per_axis(N[j], bc);
+        p.M[j] = m;
+        total *= m;
+    }
+    p.total = total;
+    p.nit = newton_iters_for(p.h);
+    p.cond_ok = (dt <= (1.0 - 2.0 * d * p.kappa) * (1.0 + 1e-12)) && p.kappa > 0.0 &&
+                p.kappa < 1.0 / (2.0 * d);
+    return p.cond_ok ? ACE_OK : ACE_W_CONDITIONS;
+}
+
+Shape shape_of(const Problem &p)
+{
+    Shape s;
+    s.d = p.d;
+    s.bc = p.bc;
+    if (p.d == 1) {
+        s.M0 = 1;
+        s.M1 = 1;
+        s.M2 = p.M[0];
+    } else if (p.d == 2) {
+        s.M0 = 1;
+        s.M1 = p.M[0];
+        s.M2 = p.M[1];
+    } else {
+        s.M0 = p.M[0];
+        s.M1 = p.M[1];
+        s.M2 = p.M[2];
+    }
+    return s;
+}
+
+StepCoef coef_of(const Problem &p)
+{
+    StepCoef c;
+    c.kappa = p.kappa;
+    c.h = p.h;
+    c.omh = 1.0 - p.h;
+    c.h3 = 3.0 * p.h;
+    c.nit = p.nit;
+    return c;
+}
+
+double energy_from(const Problem &p, const double *trip)
+{
+    // E = dx^d [ sum (phi^2-1)^2/4 + kappa/(2 dt) sum_edges (dphi)^2 ]
+    return pow(p.dx, p.d) * (trip[0] + p.kappa / (2.0 * p.dt) * trip[1]);
+}
+
+int grow(double **ptr, int64_t *cap, int64_t need)
+{
+    if (*cap >= need && *ptr) return ACE_OK;
+    if (*ptr) (void)hipFree(*ptr);
+    *ptr = nullptr;
+    *cap = 0;
+    hipError_t e = hipMalloc((void **)ptr, (size_t)need * sizeof(double));
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        return hip_status(e);
+    }
+    *cap = need;
+    return ACE_OK;
+}
+
+}  // namespace ace
+
+#define ACE_TRY(expr)                  \
+    do {                               \
+        const int _rc = (expr);        \
+        if (_rc < 0) return _rc;       \
+    } while (0)
+#define ACE_HIP(expr) ACE_TRY(hip_status(expr))
+
+// ---------------------------------------------------------------------------
+// solver handle
+// ---------------------------------------------------------------------------
+
+struct ace_solver {
+    Problem p;
+    Shape shape;
+    StepCoef coef;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    double *own[2] = {nullptr, nullptr};
+    double *buf[2] = {nullptr, nullptr};
+    int cur = 0;
+    double *partials = nullptr;
+    int64_t partials_cap = 0;
+    double *mon = nullptr;  // device monitor triples
+    int64_t mon_cap = 0;
+    double *pinned = nullptr;  // host pinned scratch (3 doubles)
+    int64_t steps = 0;
+    int kernel = ACE_KERNEL_AUTO;
+    int depth = 0;
+    int tuned_kernel = 0;  // autotuned choice for ACE_KERNEL_AUTO (0: none)
+    // reverse mode
+    double *ckpt = nullptr;
+    int64_t ckpt_cap = 0;
+    int64_t ck_every = 0, ck_steps = 0, ck_count = 0;
+    int64_t ck_field_version = -1;
+    double *seg = nullptr;
+    int64_t seg_cap = 0;
+    double *lam = nullptr;
+    int64_t lam_cap = 0;
+    double *gpart = nullptr;
+    int64_t gpart_cap = 0;
+    double *gsum = nullptr;
+    int64_t field_version = 0;
+};
+
+namespace {
+
+int effective_kernel(const ace_solver *s)
+{
+    int k = s->kernel;
+    if (k == ACE_KERNEL_AUTO) k = s->tuned_kernel;
+    if (k == ACE_KERNEL_AUTO) {
+        if (s->p.total <= RESIDENT_MAX) k = ACE_KERNEL_RESIDENT;
+        else if (s->p.d == 3) k = ACE_KERNEL_MARCH;
+        else k = ACE_KERNEL_DIRECT;
+    }
+    if (k == ACE_KERNEL_RESIDENT && s->p.total > RESIDENT_MAX) k = ACE_KERNEL_DIRECT;
+    if (k == ACE_KERNEL_MARCH && !march_supported(s->shape)) k = ACE_KERNEL_DIRECT;
+    if (k == ACE_KERNEL_TBLOCK) k = ACE_KERNEL_DIRECT;
+    return k;
+}
+
+// One step from buf[cur] into buf[cur^1] with a single-step kernel; if
+// want_mon, the monitor partials of the input are left in s->partials and
+// their count in *nparts.
+int one_step(ace_solver *s, int kernel, bool want_mon, int64_t *nparts)
+{
+    const double *in = s->buf[s->cur];
+    double *out = s->buf[s->cur ^ 1];
+    double *parts = want_mon ? s->partials : nullptr;
+    hipError_t e;
+    if (kernel == ACE_KERNEL_MARCH) e = launch_step_march(s->shape, s->coef, in, out, parts, nparts, s->stream);
+    else e = launch_step_direct(s->shape, s->coef, in, out, parts, nparts, s->stream);
+    ACE_HIP(e);
+    s->cur ^= 1;
+    s->steps += 1;
+    return ACE_OK;
+}
+
+int advance(ace_solver *s, int64_t nsteps)
+{
+    if (nsteps <= 0) return ACE_OK;
+    const int k = effective_kernel(s);
+    if (k == ACE_KERNEL_RESIDENT) {
+        ACE_HIP(launch_resident(s->shape, s->coef, s->buf[s->cur], nsteps, 0, nullptr, s->stream));
+        s->steps += nsteps;
+        return ACE_OK;
+    }
+    for (int64_t i = 0; i < nsteps; ++i) ACE_TRY(one_step(s, k, false, nullptr));
+    return ACE_OK;
+}
+
+int alloc_fields(ace_solver *s)
+{
+    for (int i = 0; i < 2; ++i) {
+        hipError_t e = hipMalloc((void **)&s->own[i], (size_t)s->p.total * sizeof(double));
+        if (e != hipSuccess) return hip_status(e);
+        s->buf[i] = s->own[i];
+    }
+    const int64_t need = std::max<int64_t>(
+        std::max<int64_t>(monitor_partials_needed(s->shape), 1), 1) * 3;
+    int64_t need2 = need;
+    if (march_supported(s->shape)) need2 = std::max<int64_t>(need2, 3 * march_partials_needed(s->shape));
+    ACE_TRY(grow(&s->partials, &s->partials_cap, need2));
+    ACE_HIP(hipHostMalloc((void **)&s->pinned, 64 * sizeof(double), hipHostMallocDefault));
+    return ACE_OK;
+}
+
+int read_triple(ace_solver *s, const double *dev, double *host3)
+{
+    ACE_HIP(hipMemcpyAsync(s->pinned, dev, 3 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    ACE_HIP(hipStreamSynchronize(s->stream));
+    memcpy(host3, s->pinned, 3 * sizeof(double));
+    return ACE_OK;
+}
+
+// Monitor triple of the current field into dev_out[0..2] (stream-ordered).
+int monitor_now(ace_solver *s, double *dev_out)
+{
+    int64_t np = 0;
+    ACE_HIP(launch_monitor(s->shape, s->buf[s->cur], s->partials, &np, s->stream));
+    ACE_HIP(launch_reduce(s->partials, np, dev_out, s->stream));
+    return ACE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ace_version(void) { return "ace-mi355x 0.1 (gfx950, fp64)"; }
+
+const char *ace_strerror(int st)
+{
+    switch (st) {
+    case ACE_OK: return "ok";
+    case ACE_E_ARG: return "invalid argument";
+    case ACE_E_SIZE: return "too few cells for the boundary condition";
+    case ACE_E_ANISO: return "grid spacing differs between axes";
+    case ACE_E_DT: return "time step outside (0, 2): the cubic has no unique real root";
+    case ACE_E_HIP: return "HIP runtime error";
+    case ACE_E_NOMEM: return "out of memory";
+    case ACE_E_NONFINITE: return "non-finite value in the field";
+    case ACE_E_STATE: return "call not valid in the current state";
+    case ACE_W_CONDITIONS: return "warning: dt > 1 - 2 d kappa (maximum-principle condition fails)";
+    case ACE_W_PHI0_GT1: return "warning: |phi0| > 1 somewhere";
+    case ACE_W_MAXPRINCIPLE: return "warning: max-norm exceeded 1 under the step condition";
+    case ACE_W_ENERGY_UP: return "warning: energy increased under the step condition";
+    default: return "unknown status";
+    }
+}
+
+int ace_create(int d, const int64_t *N, const double *L, const double *R, double eps, double dt,
+               int bc, ace_solver **out)
+{
+    if (!out) return ACE_E_ARG;
+    *out = nullptr;
+    Problem p;
+    const int rc = derive(d, N, L, R, eps, dt, bc, p);
+    if (rc < 0) return rc;
+    ace_solver *s = new (std::nothrow) ace_solver();
+    if (!s) return ACE_E_NOMEM;
+    s->p = p;
+    s->shape = shape_of(p);
+    s->coef = coef_of(p);
+    (void)hipGetDevice(&s->device);
+    const int arc = alloc_fields(s);
+    if (arc < 0) {
+        ace_destroy(s);
+        return arc;
+    }
+    hipError_t e = hipMalloc((void **)&s->gsum, 4 * sizeof(double));
+    if (e != hipSuccess) {
+        ace_destroy(s);
+        return hip_status(e);
+    }
+    *out = s;
+    return rc;
+}
+
+int ace_destroy(ace_solver *s)
+{
+    if (!s) return ACE_E_ARG;
+    for (int i = 0; i < 2; ++i)
+        if (s->own[i]) (void)hipFree(s->own[i]);
+    double *devs[] = {s->partials, s->mon, s->ckpt, s->seg, s->lam, s->gpart, s->gsum};
+    for (double *p : devs)
+        if (p) (void)hipFree(p);
+    if (s->pinned) (void)hipHostFree(s->pinned);
+    delete s;
+    return ACE_OK;
+}
+
+int ace_shape(const ace_solver *s, int64_t M[3], int64_t *total)
+{
+    if (!s) return ACE_E_ARG;
+    if (M)
+        for (int j = 0; j < 3; ++j) M[j] = s->p.M[j];
+    if (total) *total = s->p.total;
+    return ACE_OK;
+}
+
+int ace_node_coords(const ace_solver *s, int axis, double *x)
+{
+    if (!s || !x || axis < 0 || axis >= s->p.d) return ACE_E_ARG;
+    const double L = s->p.L[axis], dx = s->p.dx;
+    for (int64_t i = 0; i < s->p.M[axis]; ++i) {
+        // Sec. 2: x_i = dx (i - 1/2) for HN, dx i for HD (i = 1..N-1) and P
+        if (s->p.bc == ACE_BC_HN) x[i] = L + ((double)i - 0.5) * dx;
+        else if (s->p.bc == ACE_BC_HD) x[i] = L + (double)(i + 1) * dx;
+        else x[i] = L + (double)i * dx;
+    }
+    return ACE_OK;
+}
+
+int ace_params(const ace_solver *s, ace_params_t *q)
+{
+    if (!s || !q) return ACE_E_ARG;
+    memset(q, 0, sizeof(*q));
+    const Problem &p = s->p;
+    q->d = p.d;
+    q->bc = p.bc;
+    for (int j = 0; j < 3; ++j) {
+        q->N[j] = p.N[j];
+        q->M[j] = p.M[j];
+    }
+    q->total = p.total;
+    q->dx = p.dx;
+    q->dt = p.dt;
+    q->eps = p.eps;
+    q->kappa = p.kappa;
+    q->h = p.h;
+    q->dt_bound = p.dx * p.dx / (p.dx * p.dx + 2.0 * p.d * p.eps * p.eps);
+    // Sec. 4: omega_1 = 1/3, 1/5, 1/6 for d = 1, 2, 3; s = omega_1 / kappa
+    q->omega1 = (p.d == 1) ? 1.0 / 3.0 : (p.d == 2 ? 0.2 : 1.0 / 6.0);
+    q->s = q->omega1 / p.kappa;
+    q->conditions_ok = p.cond_ok;
+    q->newton_iters = p.nit;
+    return ACE_OK;
+}
+
+int ace_set_stream(ace_solver *s, void *st)
+{
+    if (!s) return ACE_E_ARG;
+    s->stream = (hipStream_t)st;
+    return ACE_OK;
+}
+
+int ace_bind_fields(ace_solver *s, double *a, double *b)
+{
+    if (!s) return ACE_E_ARG;
+    if ((a == nullptr) != (b == nullptr) || (a && a == b)) return ACE_E_ARG;
+    if (a) {
+        s->buf[0] = a;
+        s->buf[1] = b;
+    } else {
+        s->buf[0] = s->own[0];
+        s->buf[1] = s->own[1];
+    }
+    s->cur = 0;
+    s->steps = 0;
+    s->field_version++;
+    return ACE_OK;
+}
+
+int ace_set_kernel(ace_solver *s, int kernel, int depth)
+{
+    if (!s || kernel < ACE_KERNEL_AUTO || kernel > ACE_KERNEL_TBLOCK || depth < 0) return ACE_E_ARG;
+    s->kernel = kernel;
+    s->depth = depth;
+    return ACE_OK;
+}
+
+int ace_set_phi0(ace_solver *s, const double *phi0, int where)
+{
+    if (!s || !phi0 || (where != ACE_HOST && where != ACE_DEVICE)) return ACE_E_ARG;
+    int warn = ACE_OK;
+    const size_t bytes = (size_t)s->p.total * sizeof(double);
+    if (where == ACE_HOST) {
+        for (int64_t i = 0; i < s->p.total; ++i) {
+            if (!isfinite(phi0[i])) return ACE_E_NONFINITE;
+            if (fabs(phi0[i]) > 1.0) warn = ACE_W_PHI0_GT1;
+        }
+        ACE_HIP(hipMemcpyAsync(s->buf[0], phi0, bytes, hipMemcpyHostToDevice, s->stream));
+        ACE_HIP(hipStreamSynchronize(s->stream));
+    } else {
+        ACE_HIP(hipMemcpyAsync(s->buf[0], phi0, bytes, hipMemcpyDeviceToDevice, s->stream));
+    }
+    s->cur = 0;
+    s->steps = 0;
+    s->field_version++;
+    return warn;
+}
+
+int ace_step(ace_solver *s, int64_t nsteps)
+{
+    if (!s || nsteps < 0) return ACE_E_ARG;
+    ACE_TRY(advance(s, nsteps));
+    s->field_version++;
+    return ACE_OK;
+}
+
+int ace_run_monitored(ace_solver *s, int64_t nsteps, int64_t every, double *E, double *maxn)
+{
+    if (!s || nsteps < 0 || every < 1 || !E || !maxn) return ACE_E_ARG;
+    const int64_t nmon = nsteps / every + 1;
+    ACE_TRY(grow(&s->mon, &s->mon_cap, 3 * nmon));
+    const int k = effective_kernel(s);
+    if (k == ACE_KERNEL_RESIDENT) {
+        ACE_HIP(launch_resident(s->shape, s->coef, s->buf[s->cur], nsteps, every, s->mon, s->stream));
+        s->steps += nsteps;
+    } else {
+        int64_t j = 0;
+        for (int64_t st = 0; st <= nsteps; st += every) {
+            if (st == nsteps) {
+                ACE_TRY(monitor_now(s, s->mon + 3 * j));
+            } else {
+                int64_t np = 0;
+                ACE_TRY(one_step(s, k, true, &np));
+                ACE_HIP(launch_reduce(s->partials, np, s->mon + 3 * j, s->stream));
+                const int64_t rest = std::min<int64_t>(every, nsteps - st) - 1;
+                for (int64_t i = 0; i < rest; ++i) ACE_TRY(one_step(s, k, false, nullptr));
+            }
+            ++j;
+        }
+    }
+    s->field_version++;
+    std::vector<double> trip((size_t)(3 * nmon));
+    ACE_HIP(hipMemcpyAsync(trip.data(), s->mon, trip.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           s->stream));
+    ACE_HIP(hipStreamSynchronize(s->stream));
+    int warn = ACE_OK;
+    for (int64_t j = 0; j < nmon; ++j) {
+        E[j] = energy_from(s->p, &trip[3 * j]);
+        maxn[j] = trip[3 * j + 2];
+        if (!isfinite(maxn[j]) || !isfinite(E[j])) return ACE_E_NONFINITE;
+        if (s->p.cond_ok) {
+            if (maxn[j] > 1.0 + 4.0 * 0x1p-53 && warn == ACE_OK) warn = ACE_W_MAXPRINCIPLE;
+            if (j > 0 && E[j] > E[j - 1] + 1e-14 * fabs(E[j - 1]) && warn == ACE_OK)
+                warn = ACE_W_ENERGY_UP;
+        }
+    }
+    return warn;
+}
+
+int ace_energy(ace_solver *s, double *E)
+{
+    if (!s || !E) return ACE_E_ARG;
+    ACE_TRY(grow(&s->mon, &s->mon_cap, 3));
+    ACE_TRY(monitor_now(s, s->mon));
+    double t[3];
+    ACE_TRY(read_triple(s, s->mon, t));
+    *E = energy_from(s->p, t);
+    return isfinite(*E) ? ACE_OK : ACE_E_NONFINITE;
+}
+
+int ace_maxnorm(ace_solver *s, double *m)
+{
+    if (!s || !m) return ACE_E_ARG;
+    ACE_TRY(grow(&s->mon, &s->mon_cap, 3));
+    ACE_TRY(monitor_now(s, s->mon));
+    double t[3];
+    ACE_TRY(read_triple(s, s->mon, t));
+    *m = t[2];
+    return isfinite(*m) ? ACE_OK : ACE_E_NONFINITE;
+}
+
+int ace_get_phi(ace_solver *s, double *out, int where)
+{
+    if (!s || !out || (where != ACE_HOST && where != ACE_DEVICE)) return ACE_E_ARG;
+    const size_t bytes = (size_t)s->p.total * sizeof(double);
+    ACE_HIP(hipMemcpyAsync(out, s->buf[s->cur], bytes,
+                           where == ACE_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                           s->stream));
+    if (where == ACE_HOST) ACE_HIP(hipStreamSynchronize(s->stream));
+    return ACE_OK;
+}
+
+int64_t ace_step_count(const ace_solver *s) { return s ? s->steps : -1; }
+
+const double *ace_field_ptr(const ace_solver *s) { return s ? s->buf[s->cur] : nullptr; }
+
+// ---------------------------------------------------------------------------
+// reverse mode
+// ---------------------------------------------------------------------------
+
+int ace_forward_ckpt(ace_solver *s, const double *phi0, int where, int64_t nsteps, int64_t every)
+{
+    if (!s || !phi0 || nsteps < 0 || every < 1) return ACE_E_ARG;
+    const int rc = ace_set_phi0(s, phi0, where);
+    if (rc < 0) return rc;
+    const int64_t total = s->p.total;
+    const int64_t nck = nsteps == 0 ? 1 : (nsteps + every - 1) / every;
+    ACE_TRY(grow(&s->ckpt, &s->ckpt_cap, nck * total));
+    const size_t bytes = (size_t)total * sizeof(double);
+    for (int64_t j = 0; j < nck; ++j) {
+        ACE_HIP(hipMemcpyAsync(s->ckpt + j * total, s->buf[s->cur], bytes, hipMemcpyDeviceToDevice,
+                               s->stream));
+        const int64_t n = std::min<int64_t>(every, nsteps - j * every);
+        ACE_TRY(advance(s, n));
+    }
+    s->field_version++;
+    s->ck_every = every;
+    s->ck_steps = nsteps;
+    s->ck_count = nck;
+    s->ck_field_version = s->field_version;
+    return rc;
+}
+
+int ace_backward(ace_solver *s, const double *lambdaT, double *dphi0, double *deps2, int where)
+{
+    if (!s || !lambdaT || !dphi0 || !deps2 || (where != ACE_HOST && where != ACE_DEVICE))
+        return ACE_E_ARG;
+    if (s->ck_count <= 0 || s->ck_field_version != s->field_version) return ACE_E_STATE;
+    const int64_t total = s->p.total, every = s->ck_every, nsteps = s->ck_steps;
+    const size_t bytes = (size_t)total * sizeof(double);
+    ACE_TRY(grow(&s->seg, &s->seg_cap, (every + 1) * total));
+    ACE_TRY(grow(&s->lam, &s->lam_cap, 2 * total));
+    const int64_t npart = adjoint_partials_needed(s->shape);
+    ACE_TRY(grow(&s->gpart, &s->gpart_cap, npart * every));
+    double *lam[2] = {s->lam, s->lam + total};
+    int lc = 0;
+    ACE_HIP(hipMemcpyAsync(lam[0], lambdaT, bytes,
+                           where == ACE_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                           s->stream));
+    ACE_HIP(hipMemsetAsync(s->gsum, 0, sizeof(double), s->stream));
+    // recompute segments with the single-step kernels so each state lands in
+    // its own slot of the segment buffer
+    int k = effective_kernel(s);
+    if (k == ACE_KERNEL_RESIDENT) k = ACE_KERNEL_DIRECT;
+    for (int64_t j = s->ck_count - 1; j >= 0; --j) {
+        const int64_t a = j * every;
+        const int64_t n = std::min<int64_t>(every, nsteps - a);
+        ACE_HIP(hipMemcpyAsync(s->seg, s->ckpt + j * total, bytes, hipMemcpyDeviceToDevice, s->stream));
+        for (int64_t i = 0; i < n; ++i) {
+            const double *in = s->seg + i * total;
+            double *out = s->seg + (i + 1) * total;
+            hipError_t e = (k == ACE_KERNEL_MARCH)
+                               ? launch_step_march(s->shape, s->coef, in, out, nullptr, nullptr, s->stream)
+                               : launch_step_direct(s->shape, s->coef, in, out, nullptr, nullptr, s->stream);
+            ACE_HIP(e);
+        }
+        for (int64_t i = n - 1; i >= 0; --i) {
+            ACE_HIP(launch_adjoint_step(s->shape, s->coef, lam[lc], s->seg + i * total,
+                                        s->seg + (i + 1) * total, lam[lc ^ 1],
+                                        s->gpart + i * npart, nullptr, s->stream));
+            lc ^= 1;
+        }
+        if (n > 0) ACE_HIP(launch_sum(s->gpart, n * npart, s->gsum, 1, s->stream));
+    }
+    ACE_HIP(hipMemcpyAsync(dphi0, lam[lc], bytes,
+                           where == ACE_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                           s->stream));
+    ACE_HIP(hipMemcpyAsync(s->pinned, s->gsum, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    ACE_HIP(hipStreamSynchronize(s->stream));
+    // kappa = eps^2 dt / dx^2  =>  dL/d(eps^2) = (dt / dx^2) dL/dkappa
+    *deps2 = s->pinned[0] * s->p.dt / (s->p.dx * s->p.dx);
+    return ACE_OK;
+}
+
+int ace_adjoint(ace_solver *s, const double *phi0, int64_t nsteps, int64_t ckpt_every,
+                const double *lambdaT, double *dphi0, double *deps2, int where)
+{
+    const int rc = ace_forward_ckpt(s, phi0, where, nsteps, ckpt_every);
+    if (rc < 0) return rc;
+    return ace_backward(s, lambdaT, dphi0, deps2, where);
+}
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+// Device-side building blocks of the RLB-MIE-FD step for gfx950 (wave64).
+//
+// The step (Sec. 2, pointwise form IE-FD) at a node with value p is
+//   xi    = p + kappa * sum_k (p_{+k} + p_{-k} - 2 p) - h (p^3 - p),
+//   p_new = the unique real root theta of theta + h (theta^3 - theta) = xi
+// (Sec. 3.2, Remark 1: unique for 0 < dt < 2), with h = dt/2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ace_internal.h"
+
+namespace ace {
+
+// Reciprocal of a positive double near [0.5, 4]: hardware estimate plus one
+// Newton-Raphson correction.  Only used for Newton steps on the cubic, whose
+// own iteration absorbs the remaining error.
+__device__ __forceinline__ double approx_rcp(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    const double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    return r;
+}
+
+// Unique real root of theta + h (theta^3 - theta) = xi for 0 < h < 1.
+// The root map is odd, so Newton's method runs on |xi| from theta_0 = |xi|
+// and the sign is restored: 0 and +-1 are exact fixed points of the
+// iteration, and -xi gives exactly -theta.  For |xi| <= 1 (always the case
+// under Theorem 2's conditions) `nit` steps reach about 1 ulp; the host picks
+// nit from dt.  For |xi| > 1 (only when the conditions fail) the iteration
+// continues until the correction stops mattering (at most 200 steps).
+__device__ __forceinline__ double cubic_root(double xi, const StepCoef &c)
+{
+    const double a = fabs(xi);
+    double x = a;
+    for (int k = 0; k < c.nit; ++k) {
+        const double x2 = x * x;
+        const double p = fma(c.h, fma(x, x2, -x), x - a);
+        const double dp = fma(c.h3, x2, c.omh);
+        x = fma(-p, approx_rcp(dp), x);
+    }
+    if (a > 1.0) {
+        for (int k = 0; k < 200; ++k) {
+            const double x2 = x * x;
+            const double p = fma(c.h, fma(x, x2, -x), x - a);
+            const double dp = fma(c.h3, x2, c.omh);
+            const double step = p / dp;
+            x -= step;
+            if (!(fabs(step) > 0x1p-54 * x)) break;
+        }
+    }
+    return copysign(x, xi);
+}
+
+// Explicit part xi from the node value p and the sum over axes of its two
+// neighbours' sum (nsum = sum_k (p_{+k} + p_{-k})), for d = D.
+template <int D>
+__device__ __forceinline__ double explicit_part(double p, double nsum, const StepCoef &c)
+{
+    const double lap = fma(-2.0 * D, p, nsum);
+    const double t = fma(c.kappa, lap, p);
+    const double f = fma(p, p * p, -p);
+    return fma(-c.h, f, t);
+}
+
+template <int D>
+__device__ __forceinline__ double update(double p, double nsum, const StepCoef &c)
+{
+    return cubic_root(explicit_part<D>(p, nsum, c), c);
+}
+
+// Value used for an out-of-range neighbour (rows of the paper's D matrices):
+// Neumann mirrors the node itself, Dirichlet reads the zero wall, periodic
+// reads the wrapped node `wrap`.
+template <int BC>
+__device__ __forceinline__ double outside(double self, double wrap)
+{
+    if (BC == BC_HN) return self;
+    if (BC == BC_HD) return 0.0;
+    return wrap;
+}
+
+// NaN-propagating maximum (fmax drops NaN).
+__device__ __forceinline__ double nan_max(double a, double b)
+{
+    if (a != a) return a;
+    if (b != b) return b;
+    return a > b ? a : b;
+}
+
+// Monitor terms of one node with value p: bulk (p^2 - 1)^2 / 4; the squared
+// difference along each axis to the next node (the BC's value past the last
+// node, so HN adds 0, HD adds p^2 for the wall edge, P adds the wrap edge);
+// HD also adds p^2 for the wall edge before the first node.
+struct MonAcc {
+    double bulk, grad, mx;
+};
+
+__device__ __forceinline__ void mon_zero(MonAcc &m)
+{
+    m.bulk = 0.0;
+    m.grad = 0.0;
+    m.mx = 0.0;
+}
+
+__device__ __forceinline__ double bulk_term(double p)
+{
+    const double q = fma(p, p, -1.0);
+    return 0.25 * (q * q);
+}
+
+// Wave64 butterfly sums: every lane ends with the same, order-fixed value.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = nan_max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Deterministic block reduction of (bulk, grad, max); thread 0 writes the
+// triple to out[0..2].  `lds` holds 3 * (blockDim / 64) doubles.
+__device__ __forceinline__ void block_reduce_store(MonAcc m, double *lds, double *out)
+{
+    const int lane = threadIdx.x & 63;
+    const int nthreads = blockDim.x * blockDim.y * blockDim.z;
+    const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    const int wave = tid >> 6;
+    const int nw = (nthreads + 63) >> 6;
+    (void)lane;
+    const double b = wave_sum(m.bulk);
+    const double g = wave_sum(m.grad);
+    const double x = wave_max(m.mx);
+    if ((tid & 63) == 0) {
+        lds[3 * wave + 0] = b;
+        lds[3 * wave + 1] = g;
+        lds[3 * wave + 2] = x;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double sb = 0.0, sg = 0.0, sx = 0.0;
+        for (int w = 0; w < nw; ++w) {
+            sb += lds[3 * w + 0];
+            sg += lds[3 * w + 1];
+            sx = nan_max(sx, lds[3 * w + 2]);
+        }
+        out[0] = sb;
+        out[1] = sg;
+        out[2] = sx;
+    }
+}
+
+}  // namespace ace

@@ -1,0 +1,77 @@
+// Internal declarations shared by the host runtime and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ace {
+
+enum { BC_HN = 0, BC_HD = 1, BC_P = 2 };
+
+// Per-problem coefficients of one step (Sec. 2): kappa = eps^2 dt/dx^2,
+// h = dt/2, omh = 1 - h, h3 = 3 h (the cubic's derivative is
+// 1 - h + 3 h theta^2), nit = Newton steps for |xi| <= 1.
+struct StepCoef {
+    double kappa;
+    double h;
+    double omh;
+    double h3;
+    int nit;
+};
+
+// Shape of one field: M[0] x M[1] x M[2] stored nodes in C order (unused
+// leading axes are 1: a 2D field is 1 x M1 x M2, a 1D field 1 x 1 x M2).
+struct Shape {
+    int d;
+    int bc;
+    int64_t M0, M1, M2;
+};
+
+// ---- launchers (each defined next to its kernel) ---------------------------
+
+// One step with one thread per node (neighbours through the cache).  If
+// partials is not null, each block also writes (bulk, grad, max) of `in`
+// to partials[3 * block ...] and *nparts receives the block count.
+hipError_t launch_step_direct(const Shape &s, const StepCoef &c, const double *in,
+                              double *out, double *partials, int64_t *nparts,
+                              hipStream_t st);
+
+// Monitor partials of a field without stepping.
+hipError_t launch_monitor(const Shape &s, const double *in, double *partials,
+                          int64_t *nparts, hipStream_t st);
+int64_t monitor_partials_needed(const Shape &s);
+
+// Fixed-order reduction of nparts triples to one triple at out[0..2].
+hipError_t launch_reduce(const double *partials, int64_t nparts, double *out,
+                         hipStream_t st);
+
+// Whole field in LDS: nsteps steps in one launch (total <= RESIDENT_MAX).
+// When every > 0 the monitor triple of steps 0, every, ... <= nsteps is
+// written to mon[3 j ...].  The result ends in `field` (in place).
+constexpr int64_t RESIDENT_MAX = 8000;
+hipError_t launch_resident(const Shape &s, const StepCoef &c, double *field,
+                           int64_t nsteps, int64_t every, double *mon,
+                           hipStream_t st);
+
+// 2D/3D: tiles of the last two axes marching along axis 0 with the current
+// plane in LDS and axis-0 neighbours in registers.  Same partials contract
+// as launch_step_direct.
+hipError_t launch_step_march(const Shape &s, const StepCoef &c, const double *in,
+                             double *out, double *partials, int64_t *nparts,
+                             hipStream_t st);
+bool march_supported(const Shape &s);
+int64_t march_partials_needed(const Shape &s);
+
+// Adjoint step (reverse sweep) for one step n: reads lam (lambda^{n+1}),
+// phin (phi^n), phin1 (phi^{n+1}); writes lam_out (lambda^n) and per-block
+// partial sums of <mu, Lambda phi^n> into gpart (count in *nparts).
+hipError_t launch_adjoint_step(const Shape &s, const StepCoef &c, const double *lam,
+                               const double *phin, const double *phin1,
+                               double *lam_out, double *gpart, int64_t *nparts,
+                               hipStream_t st);
+int64_t adjoint_partials_needed(const Shape &s);
+// Fixed-order sum of n doubles into out[0] (+= if accumulate).
+hipError_t launch_sum(const double *x, int64_t n, double *out, int accumulate,
+                      hipStream_t st);
+
+}  // namespace ace

@@ -1,0 +1,330 @@
+// Step kernels that need no tiling: one thread per node (any d, any BC),
+// the LDS-resident multi-step kernel for small fields, the standalone
+// monitor pass, and the fixed-order reductions.
+#include "ace_device.h"
+
+namespace ace {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// Neighbour sum and monitor terms of node (i0, i1, i2) read through the
+// cache.  Axis order of the sum: the paper's axes from the slowest to the
+// fastest stored index.
+template <int D, int BC, bool MON>
+__device__ __forceinline__ double node_update(const Shape &s, const StepCoef &c,
+                                              const double *__restrict__ in,
+                                              int64_t i0, int64_t i1, int64_t i2,
+                                              MonAcc &m)
+{
+    const int64_t idx = (i0 * s.M1 + i1) * s.M2 + i2;
+    const double p = in[idx];
+    double nsum = 0.0;
+    double grad = 0.0;
+    const int64_t coord[3] = {i0, i1, i2};
+    const int64_t size[3] = {s.M0, s.M1, s.M2};
+    const int64_t stride[3] = {s.M1 * s.M2, s.M2, 1};
+#pragma unroll
+    for (int a = 3 - D; a < 3; ++a) {
+        const int64_t cc = coord[a], n = size[a], st = stride[a];
+        double lo, hi;
+        if (cc > 0) lo = in[idx - st];
+        else lo = outside<BC>(p, BC == BC_P ? in[idx + (n - 1) * st] : 0.0);
+        if (cc < n - 1) hi = in[idx + st];
+        else hi = outside<BC>(p, BC == BC_P ? in[idx - (n - 1) * st] : 0.0);
+        nsum += lo + hi;
+        if (MON) {
+            const double dh = hi - p;
+            grad = fma(dh, dh, grad);
+            if (BC == BC_HD && cc == 0) grad = fma(p, p, grad);
+        }
+    }
+    if (MON) {
+        m.bulk += bulk_term(p);
+        m.grad += grad;
+        m.mx = nan_max(m.mx, fabs(p));
+    }
+    return update<D>(p, nsum, c);
+}
+
+template <int D, int BC, bool MON>
+__global__ __launch_bounds__(kBlock) void k_step_direct(Shape s, StepCoef c,
+                                                        const double *__restrict__ in,
+                                                        double *__restrict__ out,
+                                                        double *__restrict__ partials)
+{
+    __shared__ double lds[3 * (kBlock / 64)];
+    const int64_t i2 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i1 = (int64_t)blockIdx.y * blockDim.y + threadIdx.y;
+    const int64_t i0 = blockIdx.z;
+    MonAcc m;
+    mon_zero(m);
+    if (i2 < s.M2 && i1 < s.M1) {
+        const double v = node_update<D, BC, MON>(s, c, in, i0, i1, i2, m);
+        out[(i0 * s.M1 + i1) * s.M2 + i2] = v;
+    }
+    if (MON) {
+        const int64_t b = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+        block_reduce_store(m, lds, partials + 3 * b);
+    }
+}
+
+template <int D, int BC>
+__global__ __launch_bounds__(kBlock) void k_monitor(Shape s, const double *__restrict__ in,
+                                                    double *__restrict__ partials)
+{
+    __shared__ double lds[3 * (kBlock / 64)];
+    const int64_t i2 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i1 = (int64_t)blockIdx.y * blockDim.y + threadIdx.y;
+    const int64_t i0 = blockIdx.z;
+    MonAcc m;
+    mon_zero(m);
+    if (i2 < s.M2 && i1 < s.M1) {
+        const int64_t idx = (i0 * s.M1 + i1) * s.M2 + i2;
+        const double p = in[idx];
+        const int64_t coord[3] = {i0, i1, i2};
+        const int64_t size[3] = {s.M0, s.M1, s.M2};
+        const int64_t stride[3] = {s.M1 * s.M2, s.M2, 1};
+        double grad = 0.0;
+#pragma unroll
+        for (int a = 3 - D; a < 3; ++a) {
+            const int64_t cc = coord[a], n = size[a], st = stride[a];
+            double hi;
+            if (cc < n - 1) hi = in[idx + st];
+            else hi = outside<BC>(p, BC == BC_P ? in[idx - (n - 1) * st] : 0.0);
+            const double dh = hi - p;
+            grad = fma(dh, dh, grad);
+            if (BC == BC_HD && cc == 0) grad = fma(p, p, grad);
+        }
+        m.bulk = bulk_term(p);
+        m.grad = grad;
+        m.mx = fabs(p);
+    }
+    const int64_t b = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+    block_reduce_store(m, lds, partials + 3 * b);
+}
+
+void direct_grid(const Shape &s, dim3 &grid, dim3 &block)
+{
+    int bx = 1;
+    while (bx < s.M2 && bx < kBlock) bx <<= 1;
+    if (s.d == 1) bx = kBlock;
+    const int by = kBlock / bx;
+    block = dim3(bx, by, 1);
+    grid = dim3((unsigned)((s.M2 + bx - 1) / bx), (unsigned)((s.M1 + by - 1) / by), (unsigned)s.M0);
+}
+
+template <bool MON>
+hipError_t dispatch_direct(const Shape &s, const StepCoef &c, const double *in, double *out,
+                           double *partials, dim3 grid, dim3 block, hipStream_t st)
+{
+#define ACE_DIRECT(DD, BB)                                                                 \
+    if (s.d == DD && s.bc == BB) {                                                         \
+        hipLaunchKernelGGL((k_step_direct<DD, BB, MON>), grid, block, 0, st, s, c, in, out, \
+                           partials);                                                      \
+        return hipGetLastError();                                                          \
+    }
+    ACE_DIRECT(1, BC_HN) ACE_DIRECT(1, BC_HD) ACE_DIRECT(1, BC_P)
+    ACE_DIRECT(2, BC_HN) ACE_DIRECT(2, BC_HD) ACE_DIRECT(2, BC_P)
+    ACE_DIRECT(3, BC_HN) ACE_DIRECT(3, BC_HD) ACE_DIRECT(3, BC_P)
+#undef ACE_DIRECT
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Whole field resident in LDS.  One workgroup; each thread owns up to
+// kResNodes nodes and keeps their neighbours' LDS slots in registers.  Slot
+// `total` always holds 0.0 and stands for the Dirichlet wall.
+// ---------------------------------------------------------------------------
+constexpr int kResThreads = 1024;
+constexpr int kResNodes = (int)((RESIDENT_MAX + kResThreads - 1) / kResThreads);
+
+template <int D, int BC>
+__global__ __launch_bounds__(kResThreads) void k_resident(Shape s, StepCoef c,
+                                                          double *__restrict__ field,
+                                                          int64_t nsteps, int64_t every,
+                                                          double *__restrict__ mon)
+{
+    __shared__ double f[RESIDENT_MAX + 1];
+    __shared__ double red[3 * (kResThreads / 64)];
+    const int total = (int)(s.M0 * s.M1 * s.M2);
+    const int tid = threadIdx.x;
+    const int nt = blockDim.x;
+    const int M[3] = {(int)s.M0, (int)s.M1, (int)s.M2};
+    const int str[3] = {(int)(s.M1 * s.M2), (int)s.M2, 1};
+    int nb_lo[kResNodes][3], nb_hi[kResNodes][3];
+#pragma unroll
+    for (int k = 0; k < kResNodes; ++k) {
+        const int j = tid + k * nt;
+        int rem = j < total ? j : 0;
+        const int cc[3] = {rem / str[0], (rem / str[1]) % M[1], rem % M[2]};
+#pragma unroll
+        for (int a = 3 - D; a < 3; ++a) {
+            const int n = M[a], st = str[a];
+            int lo, hi;
+            if (cc[a] > 0) lo = j - st;
+            else lo = (BC == BC_HN) ? j : (BC == BC_HD ? total : j + (n - 1) * st);
+            if (cc[a] < n - 1) hi = j + st;
+            else hi = (BC == BC_HN) ? j : (BC == BC_HD ? total : j - (n - 1) * st);
+            nb_lo[k][a] = lo;
+            nb_hi[k][a] = hi;
+        }
+    }
+    for (int j = tid; j < total; j += nt) f[j] = field[j];
+    if (tid == 0) f[total] = 0.0;
+    __syncthreads();
+    int64_t jm = 0;
+    for (int64_t step = 0;; ++step) {
+        if (every > 0 && step % every == 0) {
+            MonAcc m;
+            mon_zero(m);
+#pragma unroll
+            for (int k = 0; k < kResNodes; ++k) {
+                const int j = tid + k * nt;
+                if (j < total) {
+                    const double p = f[j];
+                    double g = 0.0;
+#pragma unroll
+                    for (int a = 3 - D; a < 3; ++a) {
+                        const double dh = f[nb_hi[k][a]] - p;
+                        g = fma(dh, dh, g);
+                        if (BC == BC_HD && nb_lo[k][a] == total) g = fma(p, p, g);
+                    }
+                    m.bulk += bulk_term(p);
+                    m.grad += g;
+                    m.mx = nan_max(m.mx, fabs(p));
+                }
+            }
+            block_reduce_store(m, red, mon + 3 * jm);
+            ++jm;
+            __syncthreads();
+        }
+        if (step == nsteps) break;
+        double nv[kResNodes];
+#pragma unroll
+        for (int k = 0; k < kResNodes; ++k) {
+            const int j = tid + k * nt;
+            nv[k] = 0.0;
+            if (j < total) {
+                const double p = f[j];
+                double nsum = 0.0;
+#pragma unroll
+                for (int a = 3 - D; a < 3; ++a) nsum += f[nb_lo[k][a]] + f[nb_hi[k][a]];
+                nv[k] = update<D>(p, nsum, c);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kResNodes; ++k) {
+            const int j = tid + k * nt;
+            if (j < total) f[j] = nv[k];
+        }
+        __syncthreads();
+    }
+    for (int j = tid; j < total; j += nt) field[j] = f[j];
+}
+
+__global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ partials, int64_t n,
+                                                 double *__restrict__ out)
+{
+    __shared__ double lds[3 * 16];
+    MonAcc m;
+    mon_zero(m);
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+        m.bulk += partials[3 * j + 0];
+        m.grad += partials[3 * j + 1];
+        m.mx = nan_max(m.mx, partials[3 * j + 2]);
+    }
+    block_reduce_store(m, lds, out);
+}
+
+__global__ __launch_bounds__(1024) void k_sum(const double *__restrict__ x, int64_t n,
+                                              double *__restrict__ out, int accumulate)
+{
+    __shared__ double lds[16];
+    double v = 0.0;
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) v += x[j];
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) lds[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += lds[k];
+        out[0] = accumulate ? out[0] + t : t;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_step_direct(const Shape &s, const StepCoef &c, const double *in, double *out,
+                              double *partials, int64_t *nparts, hipStream_t st)
+{
+    dim3 grid, block;
+    direct_grid(s, grid, block);
+    if (nparts) *nparts = (int64_t)grid.x * grid.y * grid.z;
+    if (partials) return dispatch_direct<true>(s, c, in, out, partials, grid, block, st);
+    return dispatch_direct<false>(s, c, in, out, nullptr, grid, block, st);
+}
+
+int64_t monitor_partials_needed(const Shape &s)
+{
+    dim3 grid, block;
+    direct_grid(s, grid, block);
+    return (int64_t)grid.x * grid.y * grid.z;
+}
+
+hipError_t launch_monitor(const Shape &s, const double *in, double *partials, int64_t *nparts,
+                          hipStream_t st)
+{
+    dim3 grid, block;
+    direct_grid(s, grid, block);
+    if (nparts) *nparts = (int64_t)grid.x * grid.y * grid.z;
+#define ACE_MON(DD, BB)                                                                  \
+    if (s.d == DD && s.bc == BB) {                                                       \
+        hipLaunchKernelGGL((k_monitor<DD, BB>), grid, block, 0, st, s, in, partials);    \
+        return hipGetLastError();                                                        \
+    }
+    ACE_MON(1, BC_HN) ACE_MON(1, BC_HD) ACE_MON(1, BC_P)
+    ACE_MON(2, BC_HN) ACE_MON(2, BC_HD) ACE_MON(2, BC_P)
+    ACE_MON(3, BC_HN) ACE_MON(3, BC_HD) ACE_MON(3, BC_P)
+#undef ACE_MON
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce(const double *partials, int64_t nparts, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partials, nparts, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum(const double *x, int64_t n, double *out, int accumulate, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(1024), 0, st, x, n, out, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_resident(const Shape &s, const StepCoef &c, double *field, int64_t nsteps,
+                           int64_t every, double *mon, hipStream_t st)
+{
+    const int64_t total = s.M0 * s.M1 * s.M2;
+    if (total > RESIDENT_MAX || total < 1) return hipErrorInvalidValue;
+    int threads = (int)((total + 63) / 64 * 64);
+    if (threads > kResThreads) threads = kResThreads;
+    // every node index tid + k * threads must fit in kResNodes slots
+    if ((total + threads - 1) / threads > kResNodes) return hipErrorInvalidValue;
+#define ACE_RES(DD, BB)                                                                      \
+    if (s.d == DD && s.bc == BB) {                                                           \
+        hipLaunchKernelGGL((k_resident<DD, BB>), dim3(1), dim3(threads), 0, st, s, c, field, \
+                           nsteps, every, mon);                                              \
+        return hipGetLastError();                                                            \
+    }
+    ACE_RES(1, BC_HN) ACE_RES(1, BC_HD) ACE_RES(1, BC_P)
+    ACE_RES(2, BC_HN) ACE_RES(2, BC_HD) ACE_RES(2, BC_P)
+    ACE_RES(3, BC_HN) ACE_RES(3, BC_HD) ACE_RES(3, BC_P)
+#undef ACE_RES
+    return hipErrorInvalidValue;
+}
+
+}  // namespace ace

@@ -1,0 +1,140 @@
+"""The three forward workloads at full size, GPU vs the CPU oracle.
+
+1D periodic 256 cells x 2000 steps and 2D Neumann 1024^2 x 10000 steps are
+compared node by node after the full run (<= 1e-12 in phi, <= 1e-12 relative
+in every monitored energy).  The 3D periodic 512^3 workload is compared on
+sampled nodes after 1 and 20 steps in the launch configuration the benchmark
+times (each sample recomputed by the oracle on the sub-box that can influence
+it), over its full 5000 steps through the maximum principle and the energy
+decay of Theorems 2-3, and at full length on a 64^3 grid with the same
+parameters node by node.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ace():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2312_07010_amd import ace as A
+    A.lib()
+    return A
+
+
+@pytest.fixture(scope="module")
+def inputs():
+    from paper_2312_07010_amd import inputs as I
+    return I
+
+
+def _run_both(ace, orc, w, shape_check=True, kernel=None):
+    s = ace.Solver(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
+    p = orc.Problem(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
+    assert s.shape == p.shape
+    phi0 = w_field(w, s)
+    if kernel is not None:
+        s.set_kernel(kernel)
+    s.set_phi0(phi0)
+    E, m = s.run_monitored(w.steps, w.every)
+    want, Ew, mw = p.run(phi0, w.steps, w.every)
+    return s, p, E, m, want, Ew, mw
+
+
+def w_field(w, s):
+    from paper_2312_07010_amd import inputs as I
+    coords = [s.coords(a) for a in range(w.d)]
+    return I.initial_field(w, s.shape, coords)
+
+
+def _check(s, E, m, want, Ew, mw):
+    got = s.get_phi()
+    err = np.abs(got - want).max()
+    erel = np.max(np.abs(E - Ew) / np.abs(Ew))
+    print(f"max|dphi| = {err:.3e}, max rel dE = {erel:.3e}")
+    assert err <= 1e-12
+    assert erel <= 1e-12
+    assert np.abs(m - mw).max() <= 1e-12
+
+
+def test_1d_periodic_256_full(ace, orc, inputs):
+    w = inputs.W1D
+    for k in (None, ace.ACE_KERNEL_DIRECT):
+        s, p, E, m, want, Ew, mw = _run_both(ace, orc, w, kernel=k)
+        _check(s, E, m, want, Ew, mw)
+
+
+@pytest.mark.timeout(900)
+def test_2d_neumann_1024_full(ace, orc, inputs):
+    w = inputs.W2D
+    s, p, E, m, want, Ew, mw = _run_both(ace, orc, w)
+    assert s.shape == (1024, 1024)
+    _check(s, E, m, want, Ew, mw)
+    # Theorems 2-3 hold along the run (conditions satisfied)
+    assert s.params["conditions_ok"] == 1
+    assert m.max() <= 1.0
+    assert np.all(np.diff(E) <= 1e-14 * np.abs(E[:-1]))
+
+
+def _subbox_oracle(orc, w, phi0, centre, T, kappa, h):
+    """Value of node `centre` after T steps of the periodic problem, computed
+    by the oracle on the (2T+3)^3 box around it: nodes farther than T from
+    the box surface cannot be reached by boundary effects in T steps."""
+    B = 2 * T + 3
+    idx = [np.arange(c - T - 1, c + T + 2) % n for c, n in zip(centre, phi0.shape)]
+    box = phi0[np.ix_(*idx)]
+    q = orc.Problem(3, [B - 2] * 3, [0.0] * 3, [1.0] * 3, 0.1, 2 * h, "HN")
+    assert q.shape == box.shape
+    q.kappa = kappa  # same lattice parameter as the full problem
+    out, _, _ = q.run(box, T)
+    return out[T + 1, T + 1, T + 1]
+
+
+@pytest.mark.timeout(600)
+def test_3d_periodic_512_sampled(ace, orc, inputs):
+    w = inputs.W3D
+    s = ace.Solver(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
+    p = orc.Problem(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
+    assert s.shape == (512, 512, 512) and p.shape == s.shape
+    assert s.params["kappa"] == p.kappa
+    phi0 = w_field(w, s)
+    rng = np.random.default_rng(5)
+    # samples: random nodes, the periodic seams and corners, the sphere's surface
+    samples = [tuple(int(v) for v in rng.integers(0, 512, 3)) for _ in range(24)]
+    samples += [(0, 0, 0), (511, 511, 511), (0, 511, 256), (511, 0, 3), (255, 256, 511)]
+    samples += [(256, 256, 256 + 154), (256 - 154, 256, 256), (100, 400, 63), (64, 127, 128)]
+    s.set_phi0(phi0)
+    for T in (1, 20):
+        s.step(T - (1 if T == 20 else 0))
+        got = s.get_phi()
+        for c in samples:
+            want = _subbox_oracle(orc, w, phi0, c, T, p.kappa, p.h)
+            assert abs(got[c] - want) <= (2e-15 if T == 1 else 5e-14), (T, c, got[c], want)
+
+
+@pytest.mark.timeout(600)
+def test_3d_periodic_512_invariants_full_length(ace, inputs):
+    """5000 steps at 512^3: the maximum principle and the energy law hold at
+    every monitored step (Theorem 2's condition is satisfied)."""
+    w = inputs.W3D
+    s = ace.Solver(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
+    assert s.params["conditions_ok"] == 1
+    s.set_phi0(w_field(w, s))
+    E, m = s.run_monitored(w.steps, w.every)
+    assert s.last_status == ace.ACE_OK
+    assert m.max() <= 1.0 + 4 * 2.0 ** -53
+    assert np.all(np.diff(E) <= 1e-14 * np.abs(E[:-1]))
+    assert E[-1] < E[0]
+
+
+@pytest.mark.timeout(600)
+def test_3d_periodic_64_full_length(ace, orc, inputs):
+    """Same parameters as the 512^3 workload on a 64^3 grid (so the oracle can
+    run it), node by node after all 5000 steps."""
+    import dataclasses
+    w = dataclasses.replace(inputs.W3D, N=[64, 64, 64], name="3d_p_64")
+    s, p, E, m, want, Ew, mw = _run_both(ace, orc, w, kernel=ace.ACE_KERNEL_MARCH)
+    _check(s, E, m, want, Ew, mw)
