@@ -25,8 +25,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12            # MI355X HBM3E, bytes/s
 BYTES_PER_UPDATE = 16.0      # read phi^n + write phi^{n+1}
-MARCH_SRC = os.path.join(ROOT, "paper_2312_07010_amd", "csrc", "ace_march.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "march3d_p512_traffic.json")
+CSRC = os.path.join(ROOT, "paper_2312_07010_amd", "csrc")
+KERNEL_SRC = {"k_march3d": "ace_march.hip", "k_tblock3d": "ace_tblock.hip"}
 
 
 def _sha(path):
@@ -34,15 +34,19 @@ def _sha(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per step launch from the committed rocprofv3 counter runs,
-    if they were taken on the current marching-kernel source; else None."""
+def measured_traffic(kname):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE runs (scaled by a copy of known size), if they were
+    taken on the current source of that kernel and of the device header; else
+    None."""
+    path = os.path.join(ROOT, "profiles", f"{kname}_p512_traffic.json")
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
-    except (OSError, ValueError):
+        src = _sha(os.path.join(CSRC, KERNEL_SRC[kname])) + _sha(os.path.join(CSRC, "ace_device.h"))
+    except (OSError, ValueError, KeyError):
         return None
-    if t.get("kernel_src_sha") != _sha(MARCH_SRC):
+    if t.get("kernel_src_sha") != src:
         return None
     return t.get("bytes_per_launch")
 
@@ -97,6 +101,11 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the CPU baseline and the adjoint/batched side metrics")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--kernel", default="auto", choices=["auto", "march", "tblock", "direct"],
+                    help="step kernel (auto = the library's choice)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="REPS",
+                    help="only copy a 1 GiB device buffer REPS times (a plain copy kernel of "
+                         "known size, for scaling HBM counters) and report its bandwidth")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -107,9 +116,33 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
 
+    if args.calibrate_copy:
+        n = 1 << 27  # 2^27 doubles = 1 GiB
+        a = torch.rand(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.calibrate_copy):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.calibrate_copy
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n,
+                          "avg_ms": ms, "GBps_read_plus_write": 16 * n / ms / 1e6}))
+        return
+
     w = inputs.W3D
     s = ace.Solver(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
     s.use_torch_stream()
+    kid = {"auto": ace.ACE_KERNEL_AUTO, "march": ace.ACE_KERNEL_MARCH,
+           "tblock": ace.ACE_KERNEL_TBLOCK, "direct": ace.ACE_KERNEL_DIRECT}[args.kernel]
+    s.set_kernel(kid)
+    kernel, per_launch = s.get_kernel()
+    kname = {ace.ACE_KERNEL_MARCH: "k_march3d", ace.ACE_KERNEL_TBLOCK: "k_tblock3d",
+             ace.ACE_KERNEL_DIRECT: "k_step_direct"}.get(kernel, str(kernel))
     coords = [s.coords(a) for a in range(w.d)]
     phi0 = inputs.initial_field(w, s.shape, coords)
     phi0_dev = torch.tensor(phi0, device="cuda")
@@ -141,13 +174,17 @@ def main():
         print("[bench] WARNING: maximum principle or energy decay violated", file=sys.stderr)
 
     # roofline of the step kernel: average launch time over the timed region
-    avg_launch_s = gpu_ms / 1e3 / args.steps
-    achieved = BYTES_PER_UPDATE * n / avg_launch_s
-    traffic = measured_traffic()
+    # (the region holds steps/per_launch step launches plus one monitor
+    # reduction per 100 steps, a few microseconds each)
+    launches = -(-args.steps // per_launch)
+    avg_launch_s = gpu_ms / 1e3 / launches
+    bytes_per_launch = BYTES_PER_UPDATE * n * per_launch
+    achieved = bytes_per_launch / avg_launch_s
+    traffic = measured_traffic(kname)
     roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": achieved / HBM_PEAK, "traffic": traffic,
-            "kernel": "k_march3d (one step per launch)", "bytes_per_launch": BYTES_PER_UPDATE * n,
-            "avg_launch_us": avg_launch_s * 1e6}
+            "kernel": f"{kname} ({per_launch} step(s) per launch)",
+            "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_launch_s * 1e6}
 
     out = {
         "metric": "FP64 grid-pt updates/s + % HBM roofline; adjoint cost ratio; batched vs looped",

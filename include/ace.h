@@ -54,9 +54,9 @@ extern "C" {
 /* ---- kernel selection (ace_set_kernel) --------------------------------- */
 #define ACE_KERNEL_AUTO 0    /* the autotuned / default choice                */
 #define ACE_KERNEL_DIRECT 1  /* one thread per node, neighbours from cache    */
-#define ACE_KERNEL_MARCH 2   /* 2D/3D: tiles marching along axis 0, LDS planes */
+#define ACE_KERNEL_MARCH 2   /* 3D: tiles marching along axis 0, LDS planes    */
 #define ACE_KERNEL_RESIDENT 3 /* whole field in LDS, many steps per launch    */
-#define ACE_KERNEL_TBLOCK 4  /* 2D/3D: temporal blocking, `depth` steps/launch */
+#define ACE_KERNEL_TBLOCK 4  /* 3D: temporal blocking, 2 steps per launch      */
 
 typedef struct ace_solver ace_solver;
 
@@ -117,8 +117,14 @@ int ace_set_stream(ace_solver *s, void *hip_stream);
 int ace_bind_fields(ace_solver *s, double *a, double *b);
 
 /* Kernel choice for ace_step (ACE_KERNEL_*) and its temporal depth (steps
- * per launch; 0 = default).  Every choice computes the same result. */
+ * per launch; 0 = default; ACE_KERNEL_TBLOCK accepts 0 or 2).  A choice that
+ * does not apply to the handle's dimension or size falls back to
+ * ACE_KERNEL_DIRECT.  Every choice computes the same result bit for bit. */
 int ace_set_kernel(ace_solver *s, int kernel, int depth);
+
+/* The kernel ace_step will actually use (after ACE_KERNEL_AUTO, the autotuned
+ * choice and fallbacks are resolved) and its steps per launch. */
+int ace_get_kernel(const ace_solver *s, int *kernel, int *steps_per_launch);
 
 /* ---- the time step (Sec. 2, scheme IE-FD; Sec. 3.2, Remark 1) ------------ */
 

@@ -67,6 +67,7 @@ _SIGS = {
     "ace_set_stream": (ctypes.c_int, [_vp, _vp]),
     "ace_bind_fields": (ctypes.c_int, [_vp, _vp, _vp]),
     "ace_set_kernel": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    "ace_get_kernel": (ctypes.c_int, [_vp, _P(ctypes.c_int), _P(ctypes.c_int)]),
     "ace_set_phi0": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
     "ace_step": (ctypes.c_int, [_vp, _i64]),
     "ace_run_monitored": (ctypes.c_int, [_vp, _i64, _i64, _P(_dbl), _P(_dbl)]),
@@ -201,6 +202,13 @@ class Solver:
 
     def set_kernel(self, kernel, depth=0):
         _check(lib().ace_set_kernel(self._h, int(kernel), int(depth)), "ace_set_kernel")
+
+    def get_kernel(self):
+        """(kernel id, steps per launch) that ace_step will use."""
+        k = ctypes.c_int()
+        n = ctypes.c_int()
+        _check(lib().ace_get_kernel(self._h, ctypes.byref(k), ctypes.byref(n)), "ace_get_kernel")
+        return k.value, n.value
 
     def set_phi0(self, phi0):
         if _is_device(phi0):

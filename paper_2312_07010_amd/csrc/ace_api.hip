@@ -36,21 +36,39 @@ int64_t nodes_per_axis(int64_t N, int bc)
     return N;
 }
 
-// Newton steps from theta_0 = |xi| that bring the relative error of the root
-// below 2^-54 for every |xi| <= 1.  With q = 3h/(1-h) the error obeys
-// r_{k+1} <= q (1 + r_k) r_k^2 (p'' = 6 h theta <= 6h, p' >= 1 - h), starting
-// from r_0 <= h/(1-h) (the root lies in [|xi|, |xi|/(1-h)]).  One extra step
-// covers the rounding of the reciprocal and of the residual.
+// Newton steps of the device root (ace_device.h, cubic_root) needed for
+// |xi| <= 1: the same start (theta_0 = a + h a (1 - a^2) for h <= 1/2, else
+// theta_0 = a) and the same Newton
+// step are run in long double on a grid of a in (0, 1]; nit is the first step
+// count whose largest relative error against the converged root is below
+// 2^-60 (well under half an ulp, leaving room for the reciprocal estimate and
+// the rounding of the double iteration).
 int newton_iters_for(double h)
 {
-    const double q = 3.0 * h / (1.0 - h);
-    double r = h / (1.0 - h);
-    int k = 0;
-    while (r > 0x1p-54 && k < 60) {
-        r = q * (1.0 + r) * r * r + 0x1p-46 * r;
-        ++k;
+    const long double H = h;
+    const int G = 2048;
+    int need = 1;
+    for (int j = 1; j <= G + 8; ++j) {
+        long double a = (j <= G) ? (long double)j / G : 1.0L - ldexpl(1.0L, -(j - G) * 6);
+        long double ref = a;
+        for (int k = 0; k < 200; ++k) {
+            const long double p = ref + H * (ref * ref * ref - ref) - a;
+            const long double dp = 1.0L + H * (3.0L * ref * ref - 1.0L);
+            const long double nx = ref - p / dp;
+            if (nx == ref) break;
+            ref = nx;
+        }
+        long double x = (H <= 0.5L) ? a + H * a * (1.0L - a * a) : a;
+        int k = 0;
+        while (fabsl(x - ref) > ldexpl(ref, -60) && k < 60) {
+            const long double p = x + H * (x * x * x - x) - a;
+            const long double dp = 1.0L + H * (3.0L * x * x - 1.0L);
+            x -= p / dp;
+            ++k;
+        }
+        if (k > need) need = k;
     }
-    return k + 1 > 2 ? k + 1 : 2;
+    return need;
 }
 
 // Validates the ace_create arguments and fills the derived parameters.
@@ -189,6 +207,7 @@ struct ace_solver {
     int64_t steps = 0;
     int kernel = ACE_KERNEL_AUTO;
     int depth = 0;
+    int zchunk = 32;  // planes per workgroup of the temporal-blocking kernel
     int tuned_kernel = 0;  // autotuned choice for ACE_KERNEL_AUTO (0: none)
     // reverse mode
     double *ckpt = nullptr;
@@ -213,30 +232,38 @@ int effective_kernel(const ace_solver *s)
     if (k == ACE_KERNEL_AUTO) k = s->tuned_kernel;
     if (k == ACE_KERNEL_AUTO) {
         if (s->p.total <= RESIDENT_MAX) k = ACE_KERNEL_RESIDENT;
-        else if (s->p.d == 3) k = ACE_KERNEL_MARCH;
+        else if (s->p.d == 3) k = ACE_KERNEL_TBLOCK;
         else k = ACE_KERNEL_DIRECT;
     }
     if (k == ACE_KERNEL_RESIDENT && s->p.total > RESIDENT_MAX) k = ACE_KERNEL_DIRECT;
+    if (k == ACE_KERNEL_TBLOCK && !tblock_supported(s->shape)) k = ACE_KERNEL_DIRECT;
     if (k == ACE_KERNEL_MARCH && !march_supported(s->shape)) k = ACE_KERNEL_DIRECT;
-    if (k == ACE_KERNEL_TBLOCK) k = ACE_KERNEL_DIRECT;
     return k;
 }
 
-// One step from buf[cur] into buf[cur^1] with a single-step kernel; if
-// want_mon, the monitor partials of the input are left in s->partials and
-// their count in *nparts.
-int one_step(ace_solver *s, int kernel, bool want_mon, int64_t *nparts)
+// One launch from buf[cur] into buf[cur^1] advancing 1 step (or 2 with the
+// temporal-blocking kernel when at least 2 remain).  If want_mon, the monitor
+// partials of the input field are left in s->partials, their count in
+// *nparts.  Returns the number of steps taken (or a negative error).
+int launch_steps(ace_solver *s, int kernel, int64_t remaining, bool want_mon, int64_t *nparts)
 {
     const double *in = s->buf[s->cur];
     double *out = s->buf[s->cur ^ 1];
     double *parts = want_mon ? s->partials : nullptr;
     hipError_t e;
-    if (kernel == ACE_KERNEL_MARCH) e = launch_step_march(s->shape, s->coef, in, out, parts, nparts, s->stream);
-    else e = launch_step_direct(s->shape, s->coef, in, out, parts, nparts, s->stream);
+    int taken = 1;
+    if (kernel == ACE_KERNEL_TBLOCK && remaining >= 2) {
+        e = launch_step_tblock2(s->shape, s->coef, in, out, parts, nparts, s->zchunk, s->stream);
+        taken = 2;
+    } else if (kernel == ACE_KERNEL_MARCH || kernel == ACE_KERNEL_TBLOCK) {
+        e = launch_step_march(s->shape, s->coef, in, out, parts, nparts, s->stream);
+    } else {
+        e = launch_step_direct(s->shape, s->coef, in, out, parts, nparts, s->stream);
+    }
     ACE_HIP(e);
     s->cur ^= 1;
-    s->steps += 1;
-    return ACE_OK;
+    s->steps += taken;
+    return taken;
 }
 
 int advance(ace_solver *s, int64_t nsteps)
@@ -248,7 +275,11 @@ int advance(ace_solver *s, int64_t nsteps)
         s->steps += nsteps;
         return ACE_OK;
     }
-    for (int64_t i = 0; i < nsteps; ++i) ACE_TRY(one_step(s, k, false, nullptr));
+    for (int64_t i = 0; i < nsteps;) {
+        const int t = launch_steps(s, k, nsteps - i, false, nullptr);
+        if (t < 0) return t;
+        i += t;
+    }
     return ACE_OK;
 }
 
@@ -263,6 +294,8 @@ int alloc_fields(ace_solver *s)
         std::max<int64_t>(monitor_partials_needed(s->shape), 1), 1) * 3;
     int64_t need2 = need;
     if (march_supported(s->shape)) need2 = std::max<int64_t>(need2, 3 * march_partials_needed(s->shape));
+    if (tblock_supported(s->shape))
+        need2 = std::max<int64_t>(need2, 3 * tblock_partials_needed(s->shape, TBLOCK_MIN_ZCHUNK));
     ACE_TRY(grow(&s->partials, &s->partials_cap, need2));
     ACE_HIP(hipHostMalloc((void **)&s->pinned, 64 * sizeof(double), hipHostMallocDefault));
     return ACE_OK;
@@ -427,8 +460,18 @@ int ace_bind_fields(ace_solver *s, double *a, double *b)
 int ace_set_kernel(ace_solver *s, int kernel, int depth)
 {
     if (!s || kernel < ACE_KERNEL_AUTO || kernel > ACE_KERNEL_TBLOCK || depth < 0) return ACE_E_ARG;
+    if (kernel == ACE_KERNEL_TBLOCK && depth != 0 && depth != 2) return ACE_E_ARG;
     s->kernel = kernel;
     s->depth = depth;
+    return ACE_OK;
+}
+
+int ace_get_kernel(const ace_solver *s, int *kernel, int *steps_per_launch)
+{
+    if (!s || !kernel) return ACE_E_ARG;
+    const int k = effective_kernel(s);
+    *kernel = k;
+    if (steps_per_launch) *steps_per_launch = (k == ACE_KERNEL_TBLOCK) ? 2 : 1;
     return ACE_OK;
 }
 
@@ -476,11 +519,16 @@ int ace_run_monitored(ace_solver *s, int64_t nsteps, int64_t every, double *E, d
             if (st == nsteps) {
                 ACE_TRY(monitor_now(s, s->mon + 3 * j));
             } else {
+                const int64_t seg = std::min<int64_t>(every, nsteps - st);
                 int64_t np = 0;
-                ACE_TRY(one_step(s, k, true, &np));
+                int64_t done = launch_steps(s, k, seg, true, &np);
+                if (done < 0) return (int)done;
                 ACE_HIP(launch_reduce(s->partials, np, s->mon + 3 * j, s->stream));
-                const int64_t rest = std::min<int64_t>(every, nsteps - st) - 1;
-                for (int64_t i = 0; i < rest; ++i) ACE_TRY(one_step(s, k, false, nullptr));
+                while (done < seg) {
+                    const int t = launch_steps(s, k, seg - done, false, nullptr);
+                    if (t < 0) return t;
+                    done += t;
+                }
             }
             ++j;
         }
@@ -589,6 +637,7 @@ int ace_backward(ace_solver *s, const double *lambdaT, double *dphi0, double *de
     // its own slot of the segment buffer
     int k = effective_kernel(s);
     if (k == ACE_KERNEL_RESIDENT) k = ACE_KERNEL_DIRECT;
+    if (k == ACE_KERNEL_TBLOCK) k = ACE_KERNEL_MARCH;
     for (int64_t j = s->ck_count - 1; j >= 0; --j) {
         const int64_t a = j * every;
         const int64_t n = std::min<int64_t>(every, nsteps - a);

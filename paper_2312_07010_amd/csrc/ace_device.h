@@ -25,16 +25,21 @@ __device__ __forceinline__ double approx_rcp(double d)
 }
 
 // Unique real root of theta + h (theta^3 - theta) = xi for 0 < h < 1.
-// The root map is odd, so Newton's method runs on |xi| from theta_0 = |xi|
-// and the sign is restored: 0 and +-1 are exact fixed points of the
-// iteration, and -xi gives exactly -theta.  For |xi| <= 1 (always the case
-// under Theorem 2's conditions) `nit` steps reach about 1 ulp; the host picks
-// nit from dt.  For |xi| > 1 (only when the conditions fail) the iteration
-// continues until the correction stops mattering (at most 200 steps).
+// The root map is odd, so the iteration runs on a = |xi| and the sign is
+// restored.  For a <= 1 (always the case under Theorem 2's conditions) it
+// starts from the first-order expansion theta_0 = a + h a (1 - a^2) of the
+// root in h (from theta_0 = a when h > 1/2, where the expansion is poor) and
+// takes `nit` Newton steps on the cubic; the host picks nit by
+// running this same iteration in extended precision over a <= 1.  0 and 1 are
+// exact fixed points of both the start and the step, so 0 and +-1 are
+// returned exactly.  For a > 1 (only when the conditions fail) the start is
+// a and Newton continues until the correction stops mattering (at most 200
+// steps).
 __device__ __forceinline__ double cubic_root(double xi, const StepCoef &c)
 {
     const double a = fabs(xi);
-    double x = a;
+    double x = fma(c.h * a, fma(-a, a, 1.0), a);
+    if (a > 1.0 || c.h > 0.5) x = a;
     for (int k = 0; k < c.nit; ++k) {
         const double x2 = x * x;
         const double p = fma(c.h, fma(x, x2, -x), x - a);

@@ -62,6 +62,15 @@ hipError_t launch_step_march(const Shape &s, const StepCoef &c, const double *in
 bool march_supported(const Shape &s);
 int64_t march_partials_needed(const Shape &s);
 
+// 3D: two steps per launch (temporal blocking); same partials contract (the
+// monitors are those of the input field).  zchunk = planes per workgroup.
+hipError_t launch_step_tblock2(const Shape &s, const StepCoef &c, const double *in,
+                               double *out, double *partials, int64_t *nparts, int zchunk,
+                               hipStream_t st);
+bool tblock_supported(const Shape &s);
+int64_t tblock_partials_needed(const Shape &s, int zchunk);
+constexpr int TBLOCK_MIN_ZCHUNK = 8;
+
 // Adjoint step (reverse sweep) for one step n: reads lam (lambda^{n+1}),
 // phin (phi^n), phin1 (phi^{n+1}); writes lam_out (lambda^n) and per-block
 // partial sums of <mu, Lambda phi^n> into gpart (count in *nparts).

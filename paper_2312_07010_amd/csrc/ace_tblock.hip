@@ -1,0 +1,272 @@
+// 3D step kernel with temporal blocking: two time levels per HBM round trip.
+//
+// A workgroup owns a 28 x 60 output tile of the two fastest axes (i1, i2) and
+// a chunk of planes along i0.  It works on the 32 x 64 region around the tile
+// (a ring of two nodes) and marches along i0.  At each position zc of the
+// march it
+//   A. computes level 1 (phi^{n+1}) of plane zc on the whole region from
+//      level 0 (phi^n): i1/i2 neighbours from the level-0 plane in LDS, i0
+//      neighbours from a per-thread register queue;
+//   C. computes level 2 (phi^{n+2}) of plane zc-1 on the tile from level 1:
+//      i1/i2 neighbours from the previous level-1 plane in LDS, i0 neighbours
+//      from a level-1 register queue, and writes it to HBM;
+//   D. stages level-0 plane zc+1 into the other LDS buffer (one barrier per
+//      plane; both levels are double-buffered).
+// Every value is computed with exactly the arithmetic and neighbour order of
+// the one-step kernels, so two steps of this kernel equal two one-step
+// launches bit for bit; the ring is recomputed redundantly instead of being
+// exchanged between workgroups.
+//
+// Boundary conditions.  Level-0 slots outside the domain hold the value the
+// BC assigns (clamped node for Neumann, 0 for Dirichlet, wrapped node for
+// periodic), so level 1 is right at every in-domain slot, and for periodic
+// also at the ring slots (they are wrapped nodes).  For Neumann and Dirichlet
+// the level-2 update of a boundary node reads its outward neighbour from its
+// own slot (mirror) or from a zero pad instead of from the ring.
+#include "ace_device.h"
+
+namespace ace {
+
+namespace {
+
+constexpr int RX = 64;           // region width: one wavefront
+constexpr int TRW = 8;           // thread rows
+constexpr int RYT = 4;           // region rows per thread
+constexpr int RH = TRW * RYT;    // region height 32
+constexpr int OX = RX - 4;       // tile (output) width 60
+constexpr int OY = RH - 4;       // tile height 28
+constexpr int NT = RX * TRW;     // 512 threads
+constexpr int LW = RX + 2;       // LDS plane with a zero pad all around
+constexpr int LH = RH + 2;
+constexpr int LP = LW * LH;
+
+template <int BC>
+__device__ __forceinline__ int64_t map_coord2(int64_t c, int64_t n)
+{
+    if (c >= 0 && c < n) return c;
+    if (BC == BC_HN) return c < 0 ? 0 : n - 1;
+    if (BC == BC_HD) return -1;
+    if (c < 0) return c + n >= 0 ? c + n : n - 1;
+    return c - n < n ? c - n : 0;
+}
+
+template <int BC>
+__device__ __forceinline__ int64_t plane_offset2(const Shape &s, int64_t y, int64_t x)
+{
+    const int64_t my = map_coord2<BC>(y, s.M1);
+    const int64_t mx = map_coord2<BC>(x, s.M2);
+    if (my < 0 || mx < 0) return -1;
+    return my * s.M2 + mx;
+}
+
+template <int BC>
+__device__ __forceinline__ int64_t plane_base2(const Shape &s, int64_t z)
+{
+    const int64_t mz = map_coord2<BC>(z, s.M0);
+    return mz < 0 ? -1 : mz * s.M1 * s.M2;
+}
+
+__device__ __forceinline__ double load_at2(const double *__restrict__ in, int64_t base, int64_t off)
+{
+    return (base < 0 || off < 0) ? 0.0 : in[base + off];
+}
+
+template <int BC, bool MON>
+__global__ __launch_bounds__(NT) void k_tblock3d(Shape s, StepCoef c, const double *__restrict__ in,
+                                                 double *__restrict__ out,
+                                                 double *__restrict__ partials, int tiles_x,
+                                                 int tiles_y, int zchunk)
+{
+    __shared__ double L0[2 * LP];
+    __shared__ double L1[2 * LP];
+    __shared__ double red[3 * (NT / 64)];
+
+    // XCD-aware numbering (block b runs on XCD b % 8; see the one-step kernel)
+    const int64_t nblk = gridDim.x;
+    const int64_t b = blockIdx.x;
+    const int64_t t = (nblk % 8 == 0) ? (b % 8) * (nblk / 8) + b / 8 : b;
+    const int64_t ntile = (int64_t)tiles_x * tiles_y;
+    const int tile_xy = (int)(t % ntile);
+    const int chunk = (int)(t / ntile);
+    const int tile_x = tile_xy % tiles_x;
+    const int tile_y = tile_xy / tiles_x;
+
+    const int tx = threadIdx.x & (RX - 1);
+    const int tr = threadIdx.x / RX;
+    const int64_t yr0 = (int64_t)tile_y * OY - 2;  // global row of region row 0
+    const int64_t xg = (int64_t)tile_x * OX - 2 + tx;
+    const int64_t z0 = (int64_t)chunk * zchunk;
+    const int64_t z1 = (z0 + zchunk < s.M0) ? z0 + zchunk : s.M0;
+    const int64_t PS = s.M1 * s.M2;
+
+    for (int i = threadIdx.x; i < 2 * LP; i += NT) {
+        L0[i] = 0.0;
+        L1[i] = 0.0;
+    }
+
+    // per-row slot data: global load offset, own LDS slot, level-2 neighbour
+    // slots (BC-redirected), output offset (or -1)
+    int64_t off[RYT], oof[RYT];
+    int own[RYT], nym[RYT], nyp[RYT], nxm[RYT], nxp[RYT];
+    bool edge_x0 = false, edge_y0[RYT];
+#pragma unroll
+    for (int r = 0; r < RYT; ++r) {
+        const int ry = tr * RYT + r;
+        const int64_t yg = yr0 + ry;
+        off[r] = plane_offset2<BC>(s, yg, xg);
+        own[r] = (ry + 1) * LW + (tx + 1);
+        nym[r] = own[r] - LW;
+        nyp[r] = own[r] + LW;
+        nxm[r] = own[r] - 1;
+        nxp[r] = own[r] + 1;
+        if (BC != BC_P) {
+            if (yg == 0) nym[r] = (BC == BC_HN) ? own[r] : (tx + 1);
+            if (yg == s.M1 - 1) nyp[r] = (BC == BC_HN) ? own[r] : (LH - 1) * LW + (tx + 1);
+            if (xg == 0) nxm[r] = (BC == BC_HN) ? own[r] : (ry + 1) * LW;
+            if (xg == s.M2 - 1) nxp[r] = (BC == BC_HN) ? own[r] : (ry + 1) * LW + (LW - 1);
+        }
+        const bool interior = ry >= 2 && ry < RH - 2 && tx >= 2 && tx < RX - 2;
+        const bool indomain = yg >= 0 && yg < s.M1 && xg >= 0 && xg < s.M2;
+        oof[r] = (interior && indomain) ? yg * s.M2 + xg : -1;
+        edge_y0[r] = (yg == 0);
+    }
+    edge_x0 = (xg == 0);
+
+    // level-0 queue: q0 = plane zc-1, q1 = zc, q2 = zc+1, q3 = zc+2
+    double q0[RYT], q1[RYT], q2[RYT], q3[RYT];
+    {
+        const int64_t bA = plane_base2<BC>(s, z0 - 2), bB = plane_base2<BC>(s, z0 - 1);
+        const int64_t bC = plane_base2<BC>(s, z0), bD = plane_base2<BC>(s, z0 + 1);
+#pragma unroll
+        for (int r = 0; r < RYT; ++r) {
+            q0[r] = load_at2(in, bA, off[r]);
+            q1[r] = load_at2(in, bB, off[r]);
+            q2[r] = load_at2(in, bC, off[r]);
+            q3[r] = load_at2(in, bD, off[r]);
+        }
+    }
+    __syncthreads();  // zero pads written before the first staging
+#pragma unroll
+    for (int r = 0; r < RYT; ++r) L0[own[r]] = q1[r];
+    __syncthreads();
+
+    // level-1 queue: w0 = plane zc-2, w1 = zc-1, w2 = zc
+    double w0[RYT], w1[RYT], w2[RYT];
+#pragma unroll
+    for (int r = 0; r < RYT; ++r) {
+        w0[r] = 0.0;
+        w1[r] = 0.0;
+        w2[r] = 0.0;
+    }
+    MonAcc m;
+    mon_zero(m);
+    int bl0 = 0, bl1 = 0;
+    for (int64_t zc = z0 - 1;; ++zc) {
+        const double *l0 = L0 + bl0 * LP;
+        double *l1w = L1 + bl1 * LP;
+        const double *l1r = L1 + (bl1 ^ 1) * LP;
+        // --- A: level 1 of plane zc on the whole region ---
+        const bool mon_plane = MON && zc >= z0 && zc < z1;
+#pragma unroll
+        for (int r = 0; r < RYT; ++r) {
+            const double p = q1[r];
+            const double xm = l0[own[r] - 1];
+            const double xp = l0[own[r] + 1];
+            const double ym = (r > 0) ? q1[r > 0 ? r - 1 : 0] : l0[own[r] - LW];
+            const double yp = (r < RYT - 1) ? q1[r < RYT - 1 ? r + 1 : 0] : l0[own[r] + LW];
+            const double nsum = ((q0[r] + q2[r]) + (ym + yp)) + (xm + xp);
+            const double v = update<3>(p, nsum, c);
+            w2[r] = v;
+            l1w[own[r]] = v;
+            if (mon_plane && oof[r] >= 0) {
+                const double dz = q2[r] - p, dy = yp - p, dx = xp - p;
+                double g = fma(dz, dz, fma(dy, dy, dx * dx));
+                if (BC == BC_HD) {
+                    if (zc == 0) g = fma(p, p, g);
+                    if (edge_y0[r]) g = fma(p, p, g);
+                    if (edge_x0) g = fma(p, p, g);
+                }
+                m.bulk += bulk_term(p);
+                m.grad += g;
+                m.mx = nan_max(m.mx, fabs(p));
+            }
+        }
+        // --- C: level 2 of plane zc-1 on the tile ---
+        if (zc >= z0 + 1) {
+            const int64_t zo = zc - 1;
+            double *const orow = out + zo * PS;
+#pragma unroll
+            for (int r = 0; r < RYT; ++r) {
+                const double p = w1[r];
+                double zm = w0[r], zp = w2[r];
+                if (BC != BC_P) {
+                    if (zo == 0) zm = (BC == BC_HN) ? p : 0.0;
+                    if (zo == s.M0 - 1) zp = (BC == BC_HN) ? p : 0.0;
+                }
+                const double xm = l1r[nxm[r]];
+                const double xp = l1r[nxp[r]];
+                const double ym = l1r[nym[r]];
+                const double yp = l1r[nyp[r]];
+                const double nsum = ((zm + zp) + (ym + yp)) + (xm + xp);
+                const double v = update<3>(p, nsum, c);
+                if (oof[r] >= 0) orow[oof[r]] = v;
+            }
+        }
+        if (zc >= z1) break;
+        // --- advance both queues, stage level-0 plane zc+1 ---
+        const int64_t bn = (zc + 3 <= z1 + 1) ? plane_base2<BC>(s, zc + 3) : -1;
+#pragma unroll
+        for (int r = 0; r < RYT; ++r) {
+            w0[r] = w1[r];
+            w1[r] = w2[r];
+            q0[r] = q1[r];
+            q1[r] = q2[r];
+            q2[r] = q3[r];
+            q3[r] = load_at2(in, bn, off[r]);
+        }
+        bl0 ^= 1;
+        bl1 ^= 1;
+#pragma unroll
+        for (int r = 0; r < RYT; ++r) L0[bl0 * LP + own[r]] = q1[r];
+        __syncthreads();
+    }
+    if (MON) block_reduce_store(m, red, partials + 3 * t);
+}
+
+}  // namespace
+
+bool tblock_supported(const Shape &s)
+{
+    return s.d == 3 && s.M0 >= 1 && s.M1 >= 1 && s.M2 >= 1;
+}
+
+int64_t tblock_partials_needed(const Shape &s, int zchunk)
+{
+    return ((s.M2 + OX - 1) / OX) * ((s.M1 + OY - 1) / OY) * ((s.M0 + zchunk - 1) / zchunk);
+}
+
+hipError_t launch_step_tblock2(const Shape &s, const StepCoef &c, const double *in, double *out,
+                               double *partials, int64_t *nparts, int zchunk, hipStream_t st)
+{
+    if (!tblock_supported(s) || zchunk < 1) return hipErrorInvalidValue;
+    const int tiles_x = (int)((s.M2 + OX - 1) / OX);
+    const int tiles_y = (int)((s.M1 + OY - 1) / OY);
+    const int nchunks = (int)((s.M0 + zchunk - 1) / zchunk);
+    const int64_t nblk = (int64_t)tiles_x * tiles_y * nchunks;
+    if (nparts) *nparts = nblk;
+#define ACE_TB(BB)                                                                              \
+    if (s.bc == BB) {                                                                           \
+        if (partials)                                                                           \
+            hipLaunchKernelGGL((k_tblock3d<BB, true>), dim3((unsigned)nblk), dim3(NT), 0, st, s, \
+                               c, in, out, partials, tiles_x, tiles_y, zchunk);                 \
+        else                                                                                    \
+            hipLaunchKernelGGL((k_tblock3d<BB, false>), dim3((unsigned)nblk), dim3(NT), 0, st,   \
+                               s, c, in, out, partials, tiles_x, tiles_y, zchunk);              \
+        return hipGetLastError();                                                               \
+    }
+    ACE_TB(BC_HN) ACE_TB(BC_HD) ACE_TB(BC_P)
+#undef ACE_TB
+    return hipErrorInvalidValue;
+}
+
+}  // namespace ace

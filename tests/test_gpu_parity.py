@@ -55,7 +55,7 @@ def test_one_and_many_steps_all_kernels(ace, orc, d, bc, N):
     want30, _, _ = p.run(phi0, 30)
     kernels = [ace.ACE_KERNEL_DIRECT, ace.ACE_KERNEL_RESIDENT]
     if d == 3:
-        kernels.append(ace.ACE_KERNEL_MARCH)
+        kernels += [ace.ACE_KERNEL_MARCH, ace.ACE_KERNEL_TBLOCK]
     outs = []
     for k in kernels:
         s.set_kernel(k)
@@ -78,7 +78,8 @@ def test_monitored_run_matches_oracle(ace, orc, d, bc, N):
     rng = np.random.default_rng(7 + d + bc)
     phi0 = rng.uniform(-0.9, 0.9, p.shape)
     want, Ew, mw = p.run(phi0, 50, 10)
-    kernels = [ace.ACE_KERNEL_DIRECT, ace.ACE_KERNEL_RESIDENT] + ([ace.ACE_KERNEL_MARCH] if d == 3 else [])
+    kernels = [ace.ACE_KERNEL_DIRECT, ace.ACE_KERNEL_RESIDENT]
+    kernels += [ace.ACE_KERNEL_MARCH, ace.ACE_KERNEL_TBLOCK] if d == 3 else []
     for k in kernels:
         s.set_kernel(k)
         s.set_phi0(phi0)
@@ -106,7 +107,8 @@ def test_edge_cases(ace, orc):
     for d, bc, N in ((1, 1, 2), (2, 1, 2), (3, 1, 2), (1, 0, 1), (3, 0, 1), (1, 2, 3), (3, 2, 3)):
         s, p = _pair(ace, orc, d, N, bc)
         phi0 = np.random.default_rng(N).uniform(-1, 1, p.shape)
-        for k in (ace.ACE_KERNEL_DIRECT, ace.ACE_KERNEL_RESIDENT, ace.ACE_KERNEL_MARCH):
+        for k in (ace.ACE_KERNEL_DIRECT, ace.ACE_KERNEL_RESIDENT, ace.ACE_KERNEL_MARCH,
+                  ace.ACE_KERNEL_TBLOCK):
             s.set_kernel(k)
             s.set_phi0(phi0)
             s.step(5)
@@ -165,3 +167,31 @@ def test_root_across_time_steps(ace, orc, d, bc, N, dt):
     np.testing.assert_allclose(s.get_phi(), p.step(phi0), rtol=0, atol=ONE_STEP_TOL)
     s.step(19)
     np.testing.assert_allclose(s.get_phi(), p.run(phi0, 20)[0], rtol=0, atol=2e-14)
+
+
+@pytest.mark.parametrize("bc", [0, 1, 2])
+def test_3d_ragged_box_all_kernels(ace, orc, bc):
+    """A box with equal spacing but different extents, so every tile dimension
+    of the marching kernels is ragged; odd step counts mix the two-step and
+    one-step launches."""
+    N = [21, 35, 129]
+    dx = 1.0 / 64
+    R = [n * dx for n in N]
+    dt = 1e-3
+    eps = math.sqrt(0.12 * dx * dx / dt)
+    s = ace.Solver(3, N, [0.0] * 3, R, eps, dt, bc)
+    p = orc.Problem(3, N, [0.0] * 3, R, eps, dt, bc)
+    assert s.shape == p.shape
+    phi0 = np.random.default_rng(77 + bc).uniform(-1, 1, p.shape)
+    want, Ew, mw = p.run(phi0, 13, 4)
+    outs = []
+    for k in (ace.ACE_KERNEL_DIRECT, ace.ACE_KERNEL_MARCH, ace.ACE_KERNEL_TBLOCK):
+        s.set_kernel(k)
+        s.set_phi0(phi0)
+        E, m = s.run_monitored(13, 4)
+        got = s.get_phi()
+        np.testing.assert_allclose(got, want, rtol=0, atol=1e-13)
+        np.testing.assert_allclose(E, Ew, rtol=1e-12)
+        np.testing.assert_allclose(m, mw, rtol=0, atol=1e-13)
+        outs.append(got)
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
