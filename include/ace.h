@@ -116,6 +116,11 @@ int ace_set_stream(ace_solver *s, void *hip_stream);
  * handle's own buffers. */
 int ace_bind_fields(ace_solver *s, double *a, double *b);
 
+/* Changes the interface width eps > 0 (hence kappa = eps^2 dt / dx^2 and the
+ * condition flag) keeping the field and the step counter; used when eps^2 is
+ * trained.  Errors: ACE_E_ARG.  Warning: ACE_W_CONDITIONS. */
+int ace_set_eps(ace_solver *s, double eps);
+
 /* Kernel choice for ace_step (ACE_KERNEL_*) and its temporal depth (steps
  * per launch; 0 = default; ACE_KERNEL_TBLOCK accepts 0 or 2).  A choice that
  * does not apply to the handle's dimension or size falls back to
@@ -244,6 +249,14 @@ int ace_batch_step(ace_batch *b, int64_t nsteps);
 int ace_batch_monitor(ace_batch *b, double *E, double *maxn);
 int ace_batch_get_phi(ace_batch *b, int i, double *out, int where);
 int ace_batch_get_all(ace_batch *b, double *out_all, int where);
+/* Instances with at most `limit` stored nodes are stepped entirely in LDS
+ * (limit is capped at the LDS capacity, 8000 doubles); larger ones stream
+ * through their two arena slots.  Results do not depend on the choice. */
+int ace_batch_set_resident_limit(ace_batch *b, int64_t limit);
+/* Times one batch step of trial_steps steps for several resident limits on
+ * the current fields (which are restored), keeps the fastest, and writes a
+ * JSON record of the timings into json (capacity cap, may be NULL). */
+int ace_batch_autotune(ace_batch *b, int64_t trial_steps, char *json, size_t cap);
 
 /* ---- autotuner ------------------------------------------------------------ */
 

@@ -67,6 +67,7 @@ _SIGS = {
     "ace_set_stream": (ctypes.c_int, [_vp, _vp]),
     "ace_bind_fields": (ctypes.c_int, [_vp, _vp, _vp]),
     "ace_set_kernel": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    "ace_set_eps": (ctypes.c_int, [_vp, _dbl]),
     "ace_get_kernel": (ctypes.c_int, [_vp, _P(ctypes.c_int), _P(ctypes.c_int)]),
     "ace_set_phi0": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
     "ace_step": (ctypes.c_int, [_vp, _i64]),
@@ -89,6 +90,8 @@ _SIGS = {
     "ace_batch_monitor": (ctypes.c_int, [_vp, _P(_dbl), _P(_dbl)]),
     "ace_batch_get_phi": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int]),
     "ace_batch_get_all": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "ace_batch_set_resident_limit": (ctypes.c_int, [_vp, _i64]),
+    "ace_batch_autotune": (ctypes.c_int, [_vp, _i64, ctypes.c_char_p, ctypes.c_size_t]),
     "ace_autotune": (ctypes.c_int, [_vp, _i64, ctypes.c_char_p, ctypes.c_size_t]),
 }
 
@@ -200,6 +203,10 @@ class Solver:
         pb = _dev(b) if b is not None else None
         _check(lib().ace_bind_fields(self._h, pa, pb), "ace_bind_fields")
 
+    def set_eps(self, eps):
+        self.last_status = _check(lib().ace_set_eps(self._h, float(eps)), "ace_set_eps")
+        return self.last_status
+
     def set_kernel(self, kernel, depth=0):
         _check(lib().ace_set_kernel(self._h, int(kernel), int(depth)), "ace_set_kernel")
 
@@ -295,4 +302,103 @@ class Solver:
     def autotune(self, trial_steps=20):
         buf = ctypes.create_string_buffer(4096)
         _check(lib().ace_autotune(self._h, int(trial_steps), buf, 4096), "ace_autotune")
+        return buf.value.decode()
+
+
+class Batch:
+    """Many independent 1D/2D instances stepped by one persistent launch.
+
+    instances: sequence of (d, N, L, R, eps, dt, bc) tuples (N, L, R per axis).
+    """
+
+    def __init__(self, instances):
+        n = len(instances)
+        descs = (InstanceDesc * n)()
+        for i, (d, N, L, R, eps, dt, bc) in enumerate(instances):
+            D = descs[i]
+            D.d = int(d)
+            D.bc = BC[bc] if isinstance(bc, str) else int(bc)
+            for j in range(3):
+                D.N[j] = int(N[j]) if j < len(N) else 1
+                D.L[j] = float(L[j]) if j < len(L) else 0.0
+                D.R[j] = float(R[j]) if j < len(R) else 1.0
+            D.eps = float(eps)
+            D.dt = float(dt)
+        st = (ctypes.c_int * n)()
+        h = _vp()
+        rc = lib().ace_batch_create(n, descs, ctypes.byref(h), st)
+        self.status = list(st)
+        _check(rc, "ace_batch_create")
+        self._h = h
+        self.count = n
+        self.shapes, self.totals, self.offsets = [], [], []
+        for i in range(n):
+            M = (_i64 * 3)()
+            tot = _i64()
+            off = _i64()
+            _check(lib().ace_batch_shape(h, i, M, ctypes.byref(tot), ctypes.byref(off)), "ace_batch_shape")
+            d = int(instances[i][0])
+            self.shapes.append(tuple(int(M[j]) for j in range(d)))
+            self.totals.append(int(tot.value))
+            self.offsets.append(int(off.value))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ace_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        _check(lib().ace_batch_set_stream(self._h, stream), "ace_batch_set_stream")
+
+    def use_torch_stream(self):
+        self.set_stream(current_stream())
+
+    def set_phi0(self, i, phi0):
+        a, p = _host(phi0)
+        if a.size != self.totals[i]:
+            raise ValueError("phi0 has the wrong size")
+        return _check(lib().ace_batch_set_phi0(self._h, int(i), p, ACE_HOST), "ace_batch_set_phi0")
+
+    def set_all(self, fields):
+        flat = np.concatenate([np.ascontiguousarray(f, dtype=np.float64).ravel() for f in fields])
+        if flat.size != sum(self.totals):
+            raise ValueError("fields have the wrong total size")
+        return _check(lib().ace_batch_set_all(self._h, flat.ctypes.data, ACE_HOST), "ace_batch_set_all")
+
+    def step(self, nsteps):
+        return _check(lib().ace_batch_step(self._h, int(nsteps)), "ace_batch_step")
+
+    def monitor(self):
+        E = np.empty(self.count)
+        mx = np.empty(self.count)
+        _check(lib().ace_batch_monitor(self._h, E.ctypes.data_as(_P(_dbl)), mx.ctypes.data_as(_P(_dbl))),
+               "ace_batch_monitor")
+        return E, mx
+
+    def get_phi(self, i):
+        a = np.empty(self.shapes[i])
+        _check(lib().ace_batch_get_phi(self._h, int(i), a.ctypes.data, ACE_HOST), "ace_batch_get_phi")
+        return a
+
+    def get_all(self):
+        flat = np.empty(sum(self.totals))
+        _check(lib().ace_batch_get_all(self._h, flat.ctypes.data, ACE_HOST), "ace_batch_get_all")
+        out, o = [], 0
+        for shp, t in zip(self.shapes, self.totals):
+            out.append(flat[o:o + t].reshape(shp))
+            o += t
+        return out
+
+    def set_resident_limit(self, limit):
+        _check(lib().ace_batch_set_resident_limit(self._h, int(limit)), "ace_batch_set_resident_limit")
+
+    def autotune(self, trial_steps=20):
+        buf = ctypes.create_string_buffer(4096)
+        _check(lib().ace_batch_autotune(self._h, int(trial_steps), buf, 4096), "ace_batch_autotune")
         return buf.value.decode()

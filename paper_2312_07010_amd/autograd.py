@@ -1,0 +1,48 @@
+"""torch.autograd binding of the library's checkpointed reverse sweep.
+
+ACEStep.apply(phi0, eps2, solver, nsteps, ckpt_every) runs nsteps steps of
+the scheme from phi0 (a CUDA float64 tensor) with interface width
+sqrt(eps2) and returns phi^T.  Its backward calls the library's transposed
+step (ace_backward): checkpoints every ckpt_every steps are kept on the GPU
+during the forward, each segment is recomputed in the reverse sweep, and the
+gradients with respect to phi0 and eps2 come back in one pass.  All work runs
+on torch's current stream.
+"""
+import torch
+
+from . import ace as _ace
+
+
+class ACEStep(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, phi0, eps2, solver, nsteps, ckpt_every):
+        if not (phi0.is_cuda and phi0.dtype == torch.float64):
+            raise ValueError("phi0 must be a CUDA float64 tensor")
+        e2 = float(eps2.detach().item()) if torch.is_tensor(eps2) else float(eps2)
+        if not e2 > 0.0:
+            raise ValueError("eps2 must be positive")
+        solver.use_torch_stream()
+        solver.set_eps(e2 ** 0.5)
+        solver.forward_ckpt(phi0.detach().contiguous(), int(nsteps), int(ckpt_every))
+        out = torch.empty_like(phi0)
+        solver.get_phi(out)
+        ctx.solver = solver
+        ctx.eps2_is_tensor = torch.is_tensor(eps2)
+        ctx.eps2_like = eps2 if torch.is_tensor(eps2) else None
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        solver = ctx.solver
+        solver.use_torch_stream()
+        g0 = torch.empty_like(grad_out)
+        _, geps2 = solver.backward(grad_out.contiguous(), g0)
+        ge = None
+        if ctx.eps2_is_tensor:
+            ge = torch.tensor(geps2, dtype=ctx.eps2_like.dtype, device=ctx.eps2_like.device)
+        return g0, ge, None, None, None
+
+
+def ace_evolve(phi0, eps2, solver, nsteps, ckpt_every=32):
+    """phi^T after nsteps steps, differentiable in phi0 and eps2."""
+    return ACEStep.apply(phi0, eps2, solver, nsteps, ckpt_every)

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <string>
 #include <vector>
 
 #include "../../include/ace.h"
@@ -318,6 +319,32 @@ int monitor_now(ace_solver *s, double *dev_out)
     return ACE_OK;
 }
 
+// Autotuner cache: one line per tuned problem shape,
+//   ace-tune <d> <bc> <M0> <M1> <M2> <kernel> <zchunk> <ms_per_step>
+// appended by ace_autotune; the last matching line wins.
+void load_tuning(ace_solver *s)
+{
+    const char *path = getenv("ACE_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char line[256];
+    while (fgets(line, sizeof line, f)) {
+        int d, bc, k, zc;
+        long long m0, m1, m2;
+        double ms;
+        if (sscanf(line, "ace-tune %d %d %lld %lld %lld %d %d %lf", &d, &bc, &m0, &m1, &m2, &k, &zc,
+                   &ms) != 8)
+            continue;
+        if (d == s->p.d && bc == s->p.bc && m0 == s->p.M[0] && m1 == s->p.M[1] && m2 == s->p.M[2] &&
+            k >= ACE_KERNEL_DIRECT && k <= ACE_KERNEL_TBLOCK && zc >= TBLOCK_MIN_ZCHUNK) {
+            s->tuned_kernel = k;
+            s->zchunk = zc;
+        }
+    }
+    fclose(f);
+}
+
 }  // namespace
 
 extern "C" {
@@ -363,6 +390,7 @@ int ace_create(int d, const int64_t *N, const double *L, const double *R, double
         ace_destroy(s);
         return arc;
     }
+    load_tuning(s);
     hipError_t e = hipMalloc((void **)&s->gsum, 4 * sizeof(double));
     if (e != hipSuccess) {
         ace_destroy(s);
@@ -455,6 +483,18 @@ int ace_bind_fields(ace_solver *s, double *a, double *b)
     s->steps = 0;
     s->field_version++;
     return ACE_OK;
+}
+
+int ace_set_eps(ace_solver *s, double eps)
+{
+    if (!s) return ACE_E_ARG;
+    Problem q;
+    const int rc = derive(s->p.d, s->p.N, s->p.L, s->p.R, eps, s->p.dt, s->p.bc, q);
+    if (rc < 0) return rc;
+    s->p = q;
+    s->coef = coef_of(q);
+    s->ck_count = 0;  // checkpoints of the old eps are no longer valid
+    return rc;
 }
 
 int ace_set_kernel(ace_solver *s, int kernel, int depth)
@@ -588,6 +628,93 @@ int ace_get_phi(ace_solver *s, double *out, int where)
 int64_t ace_step_count(const ace_solver *s) { return s ? s->steps : -1; }
 
 const double *ace_field_ptr(const ace_solver *s) { return s ? s->buf[s->cur] : nullptr; }
+
+int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap)
+{
+    if (!s || trial_steps < 1) return ACE_E_ARG;
+    struct Cand {
+        int kernel, zchunk;
+    };
+    std::vector<Cand> cands;
+    cands.push_back({ACE_KERNEL_DIRECT, s->zchunk});
+    if (s->p.total <= RESIDENT_MAX) cands.push_back({ACE_KERNEL_RESIDENT, s->zchunk});
+    if (march_supported(s->shape)) cands.push_back({ACE_KERNEL_MARCH, s->zchunk});
+    if (tblock_supported(s->shape))
+        for (int zc : {16, 32, 64, 128})
+            if (zc <= std::max<int64_t>(s->shape.M0, 16)) cands.push_back({ACE_KERNEL_TBLOCK, zc});
+    const int64_t total = s->p.total;
+    double *save = nullptr;
+    ACE_HIP(hipMalloc((void **)&save, sizeof(double) * total));
+    const int cur0 = s->cur;
+    const int64_t steps0 = s->steps;
+    const int kernel0 = s->kernel, zchunk0 = s->zchunk;
+    int rc = hip_status(hipMemcpyAsync(save, s->buf[cur0], sizeof(double) * total,
+                                       hipMemcpyDeviceToDevice, s->stream));
+    auto restore = [&]() {
+        s->cur = cur0;
+        return hip_status(hipMemcpyAsync(s->buf[cur0], save, sizeof(double) * total,
+                                         hipMemcpyDeviceToDevice, s->stream));
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc >= 0) rc = hip_status(hipEventCreate(&e0));
+    if (rc >= 0) rc = hip_status(hipEventCreate(&e1));
+    std::string rec = "{\"kind\": \"solver\", \"trial_steps\": " + std::to_string(trial_steps) +
+                      ", \"candidates\": [";
+    double best_ms = 1e300;
+    Cand best = cands[0];
+    bool first = true;
+    for (const Cand &c : cands) {
+        if (rc < 0) break;
+        s->kernel = c.kernel;
+        s->zchunk = c.zchunk;
+        if ((rc = restore()) < 0) break;
+        if ((rc = advance(s, 2)) < 0) break;  // warm-up (loads the code object)
+        if ((rc = restore()) < 0) break;
+        if ((rc = hip_status(hipEventRecord(e0, s->stream))) < 0) break;
+        if ((rc = advance(s, trial_steps)) < 0) break;
+        if ((rc = hip_status(hipEventRecord(e1, s->stream))) < 0) break;
+        if ((rc = hip_status(hipEventSynchronize(e1))) < 0) break;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const double per = ms / (double)trial_steps;
+        char buf[200];
+        snprintf(buf, sizeof buf, "%s{\"kernel\": %d, \"zchunk\": %d, \"ms_per_step\": %.6f}",
+                 first ? "" : ", ", c.kernel, c.zchunk, per);
+        rec += buf;
+        first = false;
+        if (per < best_ms) {
+            best_ms = per;
+            best = c;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    s->kernel = kernel0;
+    s->zchunk = zchunk0;
+    if (rc >= 0) rc = restore();
+    if (rc >= 0) rc = hip_status(hipStreamSynchronize(s->stream));
+    (void)hipFree(save);
+    s->steps = steps0;
+    if (rc < 0) return rc;
+    s->tuned_kernel = best.kernel;
+    s->zchunk = best.zchunk;
+    char buf[200];
+    snprintf(buf, sizeof buf, "], \"choice\": {\"kernel\": %d, \"zchunk\": %d, \"ms_per_step\": %.6f}}",
+             best.kernel, best.zchunk, best_ms);
+    rec += buf;
+    if (json && cap > 0) snprintf(json, cap, "%s", rec.c_str());
+    const char *path = getenv("ACE_AUTOTUNE_CACHE");
+    if (path) {
+        FILE *f = fopen(path, "a");
+        if (f) {
+            fprintf(f, "ace-tune %d %d %lld %lld %lld %d %d %.6f\n", s->p.d, s->p.bc,
+                    (long long)s->p.M[0], (long long)s->p.M[1], (long long)s->p.M[2], best.kernel,
+                    best.zchunk, best_ms);
+            fclose(f);
+        }
+    }
+    return ACE_OK;
+}
 
 // ---------------------------------------------------------------------------
 // reverse mode

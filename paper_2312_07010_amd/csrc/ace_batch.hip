@@ -1,20 +1,556 @@
-// Batches of independent instances (placeholder until the persistent kernel).
+// Batches of independent 1D/2D instances in one persistent launch.
+//
+// Each workgroup repeatedly takes the next task from a queue (a global
+// counter; tasks are instances ordered by decreasing cost, so the largest
+// start first) and runs every step of that instance before taking another.
+// Instances whose field fits in LDS are stepped entirely in LDS (one global
+// read and one write per launch); larger ones ping-pong between their two
+// arena slots with a workgroup barrier between steps.  Every instance carries
+// its own shape, boundary condition, kappa, h and Newton count, and every
+// update uses the same arithmetic as the single-instance kernels, so each
+// instance's result equals ace_step on that instance bit for bit.
+//
+// The launch pair (counter reset by a one-thread kernel, then the persistent
+// kernel) is captured once per step count into a HIP graph and replayed.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
 #include "../../include/ace.h"
+#include "ace_device.h"
+#include "ace_runtime.h"
+
+namespace ace {
+
+struct BatchInst {
+    int d, bc;
+    int64_t M1, M2;   // 1D: 1 x M; 2D: M0 x M1 of the problem
+    int64_t total;
+    int64_t off;      // field offset in both arenas (doubles)
+    StepCoef c;
+    int resident;     // 1: stepped in LDS
+};
+
+namespace {
+
+constexpr int kBT = 1024;                       // threads per workgroup
+constexpr int kBNodes = (int)((RESIDENT_MAX + kBT - 1) / kBT);
+
+template <int D, int BC>
+__device__ void batch_resident(const BatchInst &I, double *__restrict__ fa, int64_t nsteps,
+                               double *f)
+{
+    const int total = (int)I.total;
+    const int tid = threadIdx.x;
+    const int M1 = (int)I.M1, M2 = (int)I.M2;
+    int nb_lo[kBNodes][2], nb_hi[kBNodes][2];
+#pragma unroll
+    for (int k = 0; k < kBNodes; ++k) {
+        const int j = tid + k * kBT;
+        const int jj = j < total ? j : 0;
+        const int cc[2] = {jj / M2, jj % M2};
+        const int n[2] = {M1, M2};
+        const int st[2] = {M2, 1};
+#pragma unroll
+        for (int a = 2 - D; a < 2; ++a) {
+            int lo, hi;
+            if (cc[a] > 0) lo = j - st[a];
+            else lo = (BC == BC_HN) ? j : (BC == BC_HD ? total : j + (n[a] - 1) * st[a]);
+            if (cc[a] < n[a] - 1) hi = j + st[a];
+            else hi = (BC == BC_HN) ? j : (BC == BC_HD ? total : j - (n[a] - 1) * st[a]);
+            nb_lo[k][a] = lo;
+            nb_hi[k][a] = hi;
+        }
+    }
+    for (int j = tid; j < total; j += kBT) f[j] = fa[j];
+    if (tid == 0) f[total] = 0.0;
+    __syncthreads();
+    for (int64_t step = 0; step < nsteps; ++step) {
+        double nv[kBNodes];
+#pragma unroll
+        for (int k = 0; k < kBNodes; ++k) {
+            const int j = tid + k * kBT;
+            nv[k] = 0.0;
+            if (j < total) {
+                double nsum = 0.0;
+#pragma unroll
+                for (int a = 2 - D; a < 2; ++a) nsum += f[nb_lo[k][a]] + f[nb_hi[k][a]];
+                nv[k] = update<D>(f[j], nsum, I.c);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kBNodes; ++k) {
+            const int j = tid + k * kBT;
+            if (j < total) f[j] = nv[k];
+        }
+        __syncthreads();
+    }
+    for (int j = tid; j < total; j += kBT) fa[j] = f[j];
+    __syncthreads();
+}
+
+// Instance too large for LDS: one wavefront per 64-node segment of a row,
+// neighbours through the cache, workgroup barrier (with its memory fence)
+// between steps; the field ping-pongs between its two arena slots.
+template <int D, int BC>
+__device__ void batch_stream(const BatchInst &I, double *__restrict__ fa, double *__restrict__ fb,
+                             int64_t nsteps)
+{
+    const int64_t M1 = I.M1, M2 = I.M2;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nw = kBT / 64;
+    const int64_t nseg = (M2 + 63) / 64;
+    for (int64_t step = 0; step < nsteps; ++step) {
+        const double *__restrict__ in = (step & 1) ? fb : fa;
+        double *__restrict__ out = (step & 1) ? fa : fb;
+        for (int64_t r = wave; r < M1 * nseg; r += nw) {
+            const int64_t i1 = r / nseg;
+            const int64_t i2 = (r - i1 * nseg) * 64 + lane;
+            if (i2 >= M2) continue;
+            const int64_t idx = i1 * M2 + i2;
+            const double p = in[idx];
+            double nsum = 0.0;
+            if (D == 2) {
+                double ylo, yhi;
+                if (i1 > 0) ylo = in[idx - M2];
+                else ylo = outside<BC>(p, BC == BC_P ? in[idx + (M1 - 1) * M2] : 0.0);
+                if (i1 < M1 - 1) yhi = in[idx + M2];
+                else yhi = outside<BC>(p, BC == BC_P ? in[idx - (M1 - 1) * M2] : 0.0);
+                nsum += ylo + yhi;
+            }
+            double xlo, xhi;
+            if (i2 > 0) xlo = in[idx - 1];
+            else xlo = outside<BC>(p, BC == BC_P ? in[idx + (M2 - 1)] : 0.0);
+            if (i2 < M2 - 1) xhi = in[idx + 1];
+            else xhi = outside<BC>(p, BC == BC_P ? in[idx - (M2 - 1)] : 0.0);
+            nsum += xlo + xhi;
+            out[idx] = update<D>(p, nsum, I.c);
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+    if (nsteps & 1) {  // result back into the first arena
+        for (int64_t j = threadIdx.x; j < M1 * M2; j += kBT) fa[j] = fb[j];
+        __threadfence_block();
+        __syncthreads();
+    }
+}
+
+__global__ void k_batch_reset(int *counter)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0;
+}
+
+__global__ __launch_bounds__(kBT) void k_batch(const BatchInst *__restrict__ inst,
+                                               const int *__restrict__ order, int ntasks,
+                                               int *__restrict__ counter, double *__restrict__ arena_a,
+                                               double *__restrict__ arena_b, int64_t nsteps)
+{
+    __shared__ double f[RESIDENT_MAX + 1];
+    __shared__ int task;
+    for (;;) {
+        if (threadIdx.x == 0) task = atomicAdd(counter, 1);
+        __syncthreads();
+        const int t = task;
+        __syncthreads();  // all threads read the task before the next fetch
+        if (t >= ntasks) break;
+        const BatchInst I = inst[order[t]];
+        double *fa = arena_a + I.off;
+        double *fb = arena_b + I.off;
+        if (I.resident) {
+            if (I.d == 1) {
+                if (I.bc == BC_HN) batch_resident<1, BC_HN>(I, fa, nsteps, f);
+                else if (I.bc == BC_HD) batch_resident<1, BC_HD>(I, fa, nsteps, f);
+                else batch_resident<1, BC_P>(I, fa, nsteps, f);
+            } else {
+                if (I.bc == BC_HN) batch_resident<2, BC_HN>(I, fa, nsteps, f);
+                else if (I.bc == BC_HD) batch_resident<2, BC_HD>(I, fa, nsteps, f);
+                else batch_resident<2, BC_P>(I, fa, nsteps, f);
+            }
+        } else if (I.d == 1) {
+            if (I.bc == BC_HN) batch_stream<1, BC_HN>(I, fa, fb, nsteps);
+            else if (I.bc == BC_HD) batch_stream<1, BC_HD>(I, fa, fb, nsteps);
+            else batch_stream<1, BC_P>(I, fa, fb, nsteps);
+        } else {
+            if (I.bc == BC_HN) batch_stream<2, BC_HN>(I, fa, fb, nsteps);
+            else if (I.bc == BC_HD) batch_stream<2, BC_HD>(I, fa, fb, nsteps);
+            else batch_stream<2, BC_P>(I, fa, fb, nsteps);
+        }
+    }
+}
+
+// Monitor triple (bulk, grad, max) of each instance: one workgroup each.
+__global__ __launch_bounds__(256) void k_batch_monitor(const BatchInst *__restrict__ inst,
+                                                       const double *__restrict__ arena_a,
+                                                       double *__restrict__ trip)
+{
+    __shared__ double lds[3 * 4];
+    const BatchInst I = inst[blockIdx.x];
+    const double *f = arena_a + I.off;
+    MonAcc m;
+    mon_zero(m);
+    for (int64_t j = threadIdx.x; j < I.total; j += blockDim.x) {
+        const int64_t i1 = j / I.M2, i2 = j - i1 * I.M2;
+        const double p = f[j];
+        double g = 0.0;
+        const int64_t cc[2] = {i1, i2};
+        const int64_t n[2] = {I.M1, I.M2};
+        const int64_t st[2] = {I.M2, 1};
+        for (int a = 2 - I.d; a < 2; ++a) {
+            double hi;
+            if (cc[a] < n[a] - 1) hi = f[j + st[a]];
+            else hi = (I.bc == BC_HN) ? p : (I.bc == BC_HD ? 0.0 : f[j - (n[a] - 1) * st[a]]);
+            const double dh = hi - p;
+            g = fma(dh, dh, g);
+            if (I.bc == BC_HD && cc[a] == 0) g = fma(p, p, g);
+        }
+        m.bulk += bulk_term(p);
+        m.grad += g;
+        m.mx = nan_max(m.mx, fabs(p));
+    }
+    block_reduce_store(m, lds, trip + 3 * blockIdx.x);
+}
+
+}  // namespace
+}  // namespace ace
+
+using namespace ace;
+
+struct ace_batch {
+    int count = 0;
+    std::vector<Problem> prob;
+    std::vector<BatchInst> host_inst;
+    std::vector<int> order;
+    int64_t arena_total = 0;
+    int64_t resident_limit = RESIDENT_MAX;  // tuned: largest field stepped in LDS
+    int device = 0;
+    hipStream_t stream = nullptr;   // caller's stream (graph launches go here)
+    hipStream_t capture = nullptr;  // private stream used only for graph capture
+    BatchInst *inst = nullptr;
+    int *order_dev = nullptr;
+    int *counter = nullptr;
+    double *arena_a = nullptr, *arena_b = nullptr;
+    double *trip = nullptr;
+    int grid = 0;
+    std::map<int64_t, hipGraphExec_t> graphs;
+    std::map<int64_t, hipGraph_t> graph_defs;
+};
+
+namespace {
+
+#define BT_TRY(expr)            \
+    do {                        \
+        const int _rc = (expr); \
+        if (_rc < 0) return _rc; \
+    } while (0)
+#define BT_HIP(expr) BT_TRY(hip_status(expr))
+
+void drop_graphs(ace_batch *b)
+{
+    for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &kv : b->graph_defs) (void)hipGraphDestroy(kv.second);
+    b->graphs.clear();
+    b->graph_defs.clear();
+}
+
+// Cost model for the queue order: node updates, with streaming instances
+// weighted by their extra memory traffic.
+int64_t task_cost(const BatchInst &I) { return I.total * (I.resident ? 1 : 3); }
+
+int upload_tasks(ace_batch *b)
+{
+    for (auto &I : b->host_inst) I.resident = (I.total <= b->resident_limit) ? 1 : 0;
+    b->order.resize(b->count);
+    std::iota(b->order.begin(), b->order.end(), 0);
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
+        return task_cost(b->host_inst[x]) > task_cost(b->host_inst[y]);
+    });
+    BT_HIP(hipMemcpy(b->inst, b->host_inst.data(), sizeof(BatchInst) * b->count,
+                     hipMemcpyHostToDevice));
+    BT_HIP(hipMemcpy(b->order_dev, b->order.data(), sizeof(int) * b->count, hipMemcpyHostToDevice));
+    drop_graphs(b);
+    return ACE_OK;
+}
+
+int get_graph(ace_batch *b, int64_t nsteps, hipGraphExec_t *out)
+{
+    auto it = b->graphs.find(nsteps);
+    if (it != b->graphs.end()) {
+        *out = it->second;
+        return ACE_OK;
+    }
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+    BT_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, b->capture, b->counter);
+    hipLaunchKernelGGL(k_batch, dim3(b->grid), dim3(kBT), 0, b->capture, b->inst, b->order_dev,
+                       b->count, b->counter, b->arena_a, b->arena_b, nsteps);
+    hipError_t le = hipGetLastError();
+    hipError_t ce = hipStreamEndCapture(b->capture, &g);
+    BT_HIP(le);
+    BT_HIP(ce);
+    hipError_t ie = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_status(ie);
+    }
+    b->graphs[nsteps] = e;
+    b->graph_defs[nsteps] = g;
+    *out = e;
+    return ACE_OK;
+}
+
+}  // namespace
 
 extern "C" {
-int ace_batch_create(int, const ace_instance_desc *, ace_batch **out, int *)
+
+int ace_batch_create(int count, const ace_instance_desc *desc, ace_batch **out, int *status)
 {
-    if (out) *out = nullptr;
-    return ACE_E_STATE;
+    if (!out || !desc || count < 1) return ACE_E_ARG;
+    *out = nullptr;
+    ace_batch *b = new (std::nothrow) ace_batch();
+    if (!b) return ACE_E_NOMEM;
+    b->count = count;
+    b->prob.resize(count);
+    b->host_inst.resize(count);
+    int worst = ACE_OK, warn = ACE_OK;
+    int64_t off = 0;
+    for (int i = 0; i < count; ++i) {
+        const ace_instance_desc &D = desc[i];
+        int rc = (D.d == 1 || D.d == 2) ? derive(D.d, D.N, D.L, D.R, D.eps, D.dt, D.bc, b->prob[i])
+                                        : ACE_E_ARG;
+        if (status) status[i] = rc;
+        if (rc < 0 && worst == ACE_OK) worst = rc;
+        if (rc > 0) warn = rc;
+        if (rc < 0) continue;
+        const Problem &p = b->prob[i];
+        BatchInst &I = b->host_inst[i];
+        I.d = p.d;
+        I.bc = p.bc;
+        I.M1 = (p.d == 1) ? 1 : p.M[0];
+        I.M2 = (p.d == 1) ? p.M[0] : p.M[1];
+        I.total = p.total;
+        I.off = off;
+        I.c = coef_of(p);
+        I.resident = 0;
+        off += (p.total + 31) / 32 * 32;  // 256-byte aligned fields
+    }
+    if (worst < 0) {
+        delete b;
+        return worst;
+    }
+    b->arena_total = off;
+    (void)hipGetDevice(&b->device);
+    int rc = ACE_OK;
+    auto fail = [&](int r) {
+        ace_batch_destroy(b);
+        return r;
+    };
+    if ((rc = hip_status(hipMalloc((void **)&b->arena_a, sizeof(double) * off))) < 0) return fail(rc);
+    if ((rc = hip_status(hipMalloc((void **)&b->arena_b, sizeof(double) * off))) < 0) return fail(rc);
+    if ((rc = hip_status(hipMemset(b->arena_a, 0, sizeof(double) * off))) < 0) return fail(rc);
+    if ((rc = hip_status(hipMalloc((void **)&b->inst, sizeof(BatchInst) * count))) < 0) return fail(rc);
+    if ((rc = hip_status(hipMalloc((void **)&b->order_dev, sizeof(int) * count))) < 0) return fail(rc);
+    if ((rc = hip_status(hipMalloc((void **)&b->counter, sizeof(int) * 64))) < 0) return fail(rc);
+    if ((rc = hip_status(hipMalloc((void **)&b->trip, sizeof(double) * 3 * count))) < 0) return fail(rc);
+    if ((rc = hip_status(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking))) < 0) return fail(rc);
+    int cus = 0, per_cu = 0;
+    if ((rc = hip_status(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                               b->device))) < 0)
+        return fail(rc);
+    if ((rc = hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, kBT, 0))) < 0)
+        return fail(rc);
+    b->grid = std::max(1, cus * std::max(1, per_cu));
+    if ((rc = upload_tasks(b)) < 0) return fail(rc);
+    *out = b;
+    return warn;
 }
-int ace_batch_destroy(ace_batch *) { return ACE_E_STATE; }
-int ace_batch_shape(const ace_batch *, int, int64_t *, int64_t *, int64_t *) { return ACE_E_STATE; }
-int ace_batch_set_stream(ace_batch *, void *) { return ACE_E_STATE; }
-int ace_batch_set_phi0(ace_batch *, int, const double *, int) { return ACE_E_STATE; }
-int ace_batch_set_all(ace_batch *, const double *, int) { return ACE_E_STATE; }
-int ace_batch_step(ace_batch *, int64_t) { return ACE_E_STATE; }
-int ace_batch_monitor(ace_batch *, double *, double *) { return ACE_E_STATE; }
-int ace_batch_get_phi(ace_batch *, int, double *, int) { return ACE_E_STATE; }
-int ace_batch_get_all(ace_batch *, double *, int) { return ACE_E_STATE; }
-int ace_autotune(ace_solver *, int64_t, char *, size_t) { return ACE_E_STATE; }
+
+int ace_batch_destroy(ace_batch *b)
+{
+    if (!b) return ACE_E_ARG;
+    drop_graphs(b);
+    void *ptrs[] = {b->arena_a, b->arena_b, b->inst, b->order_dev, b->counter, b->trip};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    delete b;
+    return ACE_OK;
 }
+
+int ace_batch_shape(const ace_batch *b, int i, int64_t M[3], int64_t *total, int64_t *offset)
+{
+    if (!b || i < 0 || i >= b->count) return ACE_E_ARG;
+    const Problem &p = b->prob[i];
+    if (M)
+        for (int j = 0; j < 3; ++j) M[j] = p.M[j];
+    if (total) *total = p.total;
+    if (offset) *offset = b->host_inst[i].off;
+    return ACE_OK;
+}
+
+int ace_batch_set_stream(ace_batch *b, void *st)
+{
+    if (!b) return ACE_E_ARG;
+    b->stream = (hipStream_t)st;
+    return ACE_OK;
+}
+
+int ace_batch_set_phi0(ace_batch *b, int i, const double *phi0, int where)
+{
+    if (!b || !phi0 || i < 0 || i >= b->count || (where != ACE_HOST && where != ACE_DEVICE))
+        return ACE_E_ARG;
+    const BatchInst &I = b->host_inst[i];
+    int warn = ACE_OK;
+    if (where == ACE_HOST) {
+        for (int64_t j = 0; j < I.total; ++j) {
+            if (!isfinite(phi0[j])) return ACE_E_NONFINITE;
+            if (fabs(phi0[j]) > 1.0) warn = ACE_W_PHI0_GT1;
+        }
+    }
+    BT_HIP(hipMemcpyAsync(b->arena_a + I.off, phi0, sizeof(double) * I.total,
+                          where == ACE_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                          b->stream));
+    if (where == ACE_HOST) BT_HIP(hipStreamSynchronize(b->stream));
+    return warn;
+}
+
+int ace_batch_set_all(ace_batch *b, const double *all, int where)
+{
+    if (!b || !all || (where != ACE_HOST && where != ACE_DEVICE)) return ACE_E_ARG;
+    int64_t src = 0;
+    int warn = ACE_OK;
+    for (int i = 0; i < b->count; ++i) {
+        const int rc = ace_batch_set_phi0(b, i, all + src, where);
+        if (rc < 0) return rc;
+        if (rc > 0) warn = rc;
+        src += b->host_inst[i].total;
+    }
+    return warn;
+}
+
+int ace_batch_step(ace_batch *b, int64_t nsteps)
+{
+    if (!b || nsteps < 0) return ACE_E_ARG;
+    if (nsteps == 0) return ACE_OK;
+    hipGraphExec_t e = nullptr;
+    BT_TRY(get_graph(b, nsteps, &e));
+    BT_HIP(hipGraphLaunch(e, b->stream));
+    return ACE_OK;
+}
+
+int ace_batch_monitor(ace_batch *b, double *E, double *maxn)
+{
+    if (!b || !E || !maxn) return ACE_E_ARG;
+    hipLaunchKernelGGL(k_batch_monitor, dim3(b->count), dim3(256), 0, b->stream, b->inst,
+                       b->arena_a, b->trip);
+    BT_HIP(hipGetLastError());
+    std::vector<double> t(3 * (size_t)b->count);
+    BT_HIP(hipMemcpyAsync(t.data(), b->trip, sizeof(double) * t.size(), hipMemcpyDeviceToHost,
+                          b->stream));
+    BT_HIP(hipStreamSynchronize(b->stream));
+    int rc = ACE_OK;
+    for (int i = 0; i < b->count; ++i) {
+        E[i] = energy_from(b->prob[i], &t[3 * i]);
+        maxn[i] = t[3 * i + 2];
+        if (!isfinite(E[i]) || !isfinite(maxn[i])) rc = ACE_E_NONFINITE;
+    }
+    return rc;
+}
+
+int ace_batch_get_phi(ace_batch *b, int i, double *out, int where)
+{
+    if (!b || !out || i < 0 || i >= b->count || (where != ACE_HOST && where != ACE_DEVICE))
+        return ACE_E_ARG;
+    const BatchInst &I = b->host_inst[i];
+    BT_HIP(hipMemcpyAsync(out, b->arena_a + I.off, sizeof(double) * I.total,
+                          where == ACE_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                          b->stream));
+    if (where == ACE_HOST) BT_HIP(hipStreamSynchronize(b->stream));
+    return ACE_OK;
+}
+
+int ace_batch_get_all(ace_batch *b, double *out, int where)
+{
+    if (!b || !out) return ACE_E_ARG;
+    int64_t dst = 0;
+    for (int i = 0; i < b->count; ++i) {
+        const int rc = ace_batch_get_phi(b, i, out + dst, where);
+        if (rc < 0) return rc;
+        dst += b->host_inst[i].total;
+    }
+    return ACE_OK;
+}
+
+int ace_batch_set_resident_limit(ace_batch *b, int64_t limit)
+{
+    if (!b || limit < 0) return ACE_E_ARG;
+    b->resident_limit = std::min<int64_t>(limit, RESIDENT_MAX);
+    return upload_tasks(b);
+}
+
+int ace_batch_autotune(ace_batch *b, int64_t trial_steps, char *json, size_t cap)
+{
+    if (!b || trial_steps < 1) return ACE_E_ARG;
+    // keep the current fields: time each candidate on a copy, then restore
+    double *save = nullptr;
+    BT_HIP(hipMalloc((void **)&save, sizeof(double) * b->arena_total));
+    auto restore = [&]() {
+        return hip_status(hipMemcpyAsync(b->arena_a, save, sizeof(double) * b->arena_total,
+                                         hipMemcpyDeviceToDevice, b->stream));
+    };
+    int rc = hip_status(hipMemcpyAsync(save, b->arena_a, sizeof(double) * b->arena_total,
+                                       hipMemcpyDeviceToDevice, b->stream));
+    const int64_t limits[] = {0, 1024, 2048, 4096, RESIDENT_MAX};
+    double best_ms = 1e300;
+    int64_t best = b->resident_limit;
+    std::string rec = "{\"kind\": \"batch\", \"trial_steps\": " + std::to_string(trial_steps) +
+                      ", \"candidates\": [";
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc >= 0) rc = hip_status(hipEventCreate(&e0));
+    if (rc >= 0) rc = hip_status(hipEventCreate(&e1));
+    bool first = true;
+    for (int64_t lim : limits) {
+        if (rc < 0) break;
+        if ((rc = ace_batch_set_resident_limit(b, lim)) < 0) break;
+        if ((rc = restore()) < 0) break;
+        if ((rc = ace_batch_step(b, trial_steps)) < 0) break;  // builds the graph, warms up
+        if ((rc = restore()) < 0) break;
+        if ((rc = hip_status(hipEventRecord(e0, b->stream))) < 0) break;
+        if ((rc = ace_batch_step(b, trial_steps)) < 0) break;
+        if ((rc = hip_status(hipEventRecord(e1, b->stream))) < 0) break;
+        if ((rc = hip_status(hipEventSynchronize(e1))) < 0) break;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        char buf[160];
+        snprintf(buf, sizeof buf, "%s{\"resident_limit\": %lld, \"ms\": %.4f}", first ? "" : ", ",
+                 (long long)lim, ms);
+        rec += buf;
+        first = false;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = lim;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc >= 0) rc = ace_batch_set_resident_limit(b, best);
+    if (rc >= 0) rc = restore();
+    if (rc >= 0) rc = hip_status(hipStreamSynchronize(b->stream));
+    (void)hipFree(save);
+    if (rc < 0) return rc;
+    rec += "], \"choice\": {\"resident_limit\": " + std::to_string(best) + "}}";
+    if (json && cap > 0) snprintf(json, cap, "%s", rec.c_str());
+    return ACE_OK;
+}
+
+}  // extern "C"

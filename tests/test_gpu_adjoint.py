@@ -1,0 +1,136 @@
+"""Reverse sweep on the GPU: the library's checkpointed adjoint against the
+oracle's (which keeps every state), against central finite differences of
+the GPU forward, and through the torch.autograd binding."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ace():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2312_07010_amd import ace as A
+    A.lib()
+    return A
+
+
+def _problem(ace, orc, d, N, bc, kappa=0.15, dt=2e-3):
+    dx = 1.0 / N
+    eps = math.sqrt(kappa / d * dx * dx / dt)
+    args = (d, [N] * d, [0.0] * d, [1.0] * d, eps, dt, bc)
+    return ace.Solver(*args), orc.Problem(*args)
+
+
+@pytest.mark.parametrize("ckpt", [1, 3, 8, 64])
+@pytest.mark.parametrize("d,bc,N", [(1, 0, 50), (1, 1, 37), (1, 2, 64), (2, 0, 20), (2, 1, 17),
+                                    (2, 2, 24), (3, 0, 9), (3, 1, 8), (3, 2, 10)])
+def test_adjoint_matches_oracle(ace, orc, d, bc, N, ckpt):
+    s, p = _problem(ace, orc, d, N, bc)
+    rng = np.random.default_rng(d * 10 + bc)
+    phi0 = rng.uniform(-0.6, 0.6, p.shape)
+    target = rng.uniform(-0.6, 0.6, p.shape)
+    nsteps = 23
+    phiT, _, _ = p.run(phi0, nsteps)
+    lam = phiT - target
+    g_or, gk_or, ge_or = p.adjoint(phi0, nsteps, lam)
+    g, ge = s.adjoint(phi0, nsteps, ckpt, lam)
+    np.testing.assert_allclose(s.get_phi(), phiT, rtol=0, atol=1e-13)
+    scale = np.abs(g_or).max()
+    np.testing.assert_allclose(g, g_or, rtol=0, atol=1e-12 * scale)
+    assert ge == pytest.approx(ge_or, rel=1e-11, abs=1e-13)
+
+
+def _loss_gpu(ace, s, phi0, target, nsteps):
+    s.set_phi0(phi0)
+    s.step(nsteps)
+    return 0.5 * np.sum((s.get_phi() - target) ** 2)
+
+
+@pytest.mark.timeout(300)
+def test_adjoint_against_central_differences_64(ace, orc):
+    """The workload's finite-difference grid: 2D Neumann, 64 x 64 stored nodes,
+    eps^2 = 1e-4, dt = 1e-3, 1000 steps, checkpoints every 32.  Directional
+    derivatives along 8 random unit directions and along eps^2 agree with
+    central differences of the GPU forward to 1e-6 relative."""
+    from paper_2312_07010_amd import inputs
+    w = inputs.WADJ
+    N = [62, 62]
+    s = ace.Solver(2, N, w.L, w.R, w.eps, w.dt, w.bc)
+    assert s.shape == (64, 64)
+    phi0 = inputs.uniform_field(s.shape, w.lo, w.hi, w.seed)
+    s.set_phi0(inputs.uniform_field(s.shape, w.lo, w.hi, w.extra["target_seed"]))
+    s.step(w.steps)
+    target = s.get_phi()
+    s.set_phi0(phi0)
+    s.step(w.steps)
+    lam = s.get_phi() - target
+    g, ge = s.adjoint(phi0, w.steps, w.extra["ckpt_every"], lam)
+    rng = np.random.default_rng(11)
+    h = 1e-6
+    for _ in range(8):
+        v = rng.standard_normal(s.shape)
+        v /= np.linalg.norm(v)
+        lp = _loss_gpu(ace, s, phi0 + h * v, target, w.steps)
+        lm = _loss_gpu(ace, s, phi0 - h * v, target, w.steps)
+        fd = (lp - lm) / (2 * h)
+        an = float(np.sum(g * v))
+        assert an == pytest.approx(fd, rel=1e-6), (an, fd)
+    e2 = w.eps ** 2
+    he = 1e-4 * e2
+    s.set_eps(math.sqrt(e2 + he))
+    lp = _loss_gpu(ace, s, phi0, target, w.steps)
+    s.set_eps(math.sqrt(e2 - he))
+    lm = _loss_gpu(ace, s, phi0, target, w.steps)
+    fd = (lp - lm) / (2 * he)
+    assert ge == pytest.approx(fd, rel=1e-6), (ge, fd)
+
+
+@pytest.mark.timeout(600)
+def test_adjoint_full_workload_512(ace, orc):
+    """2D Neumann 512 x 512, 1000 steps, checkpoints every 32, against the
+    oracle's reverse sweep over all stored states."""
+    from paper_2312_07010_amd import inputs
+    w = inputs.WADJ
+    s = ace.Solver(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
+    p = orc.Problem(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
+    assert s.shape == (512, 512)
+    phi0 = inputs.uniform_field(s.shape, w.lo, w.hi, w.seed)
+    target, _, _ = p.run(inputs.uniform_field(s.shape, w.lo, w.hi, w.extra["target_seed"]), w.steps)
+    phiT, _, _ = p.run(phi0, w.steps)
+    lam = phiT - target
+    g_or, _, ge_or = p.adjoint(phi0, w.steps, lam)
+    g, ge = s.adjoint(phi0, w.steps, w.extra["ckpt_every"], lam)
+    np.testing.assert_allclose(s.get_phi(), phiT, rtol=0, atol=1e-12)
+    scale = np.abs(g_or).max()
+    err = np.abs(g - g_or).max() / scale
+    print(f"max |dphi0 - oracle| / max|oracle| = {err:.3e}; d/deps2 {ge:.12e} vs {ge_or:.12e}")
+    assert err <= 1e-10
+    assert ge == pytest.approx(ge_or, rel=1e-10)
+
+
+def test_autograd_function(ace, orc):
+    import torch
+    from paper_2312_07010_amd.autograd import ace_evolve
+    s, p = _problem(ace, orc, 2, 30, 0)
+    rng = np.random.default_rng(3)
+    phi0 = rng.uniform(-0.5, 0.5, p.shape)
+    target = rng.uniform(-0.5, 0.5, p.shape)
+    x = torch.tensor(phi0, device="cuda", requires_grad=True)
+    e2 = torch.tensor(p.eps ** 2, dtype=torch.float64, device="cuda", requires_grad=True)
+    out = ace_evolve(x, e2, s, 40, 16)
+    loss = 0.5 * torch.sum((out - torch.tensor(target, device="cuda")) ** 2)
+    loss.backward()
+    phiT, _, _ = p.run(phi0, 40)
+    g_or, _, ge_or = p.adjoint(phi0, 40, phiT - target)
+    np.testing.assert_allclose(x.grad.cpu().numpy(), g_or, rtol=0, atol=1e-12 * np.abs(g_or).max())
+    assert e2.grad.item() == pytest.approx(ge_or, rel=1e-10)
+    # a second call with a new eps^2 re-derives kappa
+    e2b = torch.tensor(1.3 * p.eps ** 2, dtype=torch.float64, device="cuda")
+    out2 = ace_evolve(x.detach(), e2b, s, 40, 16)
+    q = orc.Problem(2, [30, 30], [0, 0], [1, 1], math.sqrt(1.3) * p.eps, p.dt, 0)
+    np.testing.assert_allclose(out2.cpu().numpy(), q.run(phi0, 40)[0], rtol=0, atol=1e-13)

@@ -1,0 +1,136 @@
+"""Batched persistent launch vs the oracle and vs single-instance ace_step."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ace():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2312_07010_amd import ace as A
+    A.lib()
+    return A
+
+
+def _mixed(seed=0):
+    """Instances spanning both dimensions, all BCs, LDS-resident and streamed
+    sizes (2D above 8000 nodes), several dt (hence Newton counts)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    sizes1 = [3, 5, 64, 255, 1000, 4096, 7997, 9000]
+    sizes2 = [3, 7, 40, 89, 90, 101, 150, 260]
+    for i, N in enumerate(sizes1 + sizes2):
+        d = 1 if i < len(sizes1) else 2
+        for bc in (0, 1, 2):
+            if (bc == 1 and N < 2) or (bc == 2 and N < 3):
+                continue
+            dt = float(rng.choice([5e-4, 0.01, 0.2]))
+            kappa = 0.8 * (1 - dt) / (2 * d) * rng.uniform(0.3, 1.0)
+            dx = 1.0 / N
+            eps = math.sqrt(kappa * dx * dx / dt)
+            out.append((d, [N] * d, [0.0] * d, [1.0] * d, eps, dt, bc))
+    return out
+
+
+@pytest.mark.parametrize("nsteps", [1, 30, 31])
+def test_batch_matches_oracle_and_single_instances(ace, orc, nsteps):
+    insts = _mixed()
+    b = ace.Batch(insts)
+    assert all(s >= 0 for s in b.status)
+    rng = np.random.default_rng(nsteps)
+    phi0 = [rng.uniform(-0.9, 0.9, shp) for shp in b.shapes]
+    b.set_all(phi0)
+    b.step(nsteps)
+    got = b.get_all()
+    E, mx = b.monitor()
+    for i, inst in enumerate(insts):
+        p = orc.Problem(*inst)
+        want, Ew, mw = p.run(phi0[i], nsteps, nsteps)
+        np.testing.assert_allclose(got[i], want, rtol=0, atol=1e-13, err_msg=str(inst))
+        assert E[i] == pytest.approx(Ew[-1], rel=1e-12)
+        assert mx[i] == pytest.approx(mw[-1], abs=1e-13)
+        s = ace.Solver(*inst)
+        s.set_phi0(phi0[i])
+        s.step(nsteps)
+        assert np.array_equal(s.get_phi(), got[i]), inst
+        s.close()
+
+
+def test_resident_limit_does_not_change_results(ace):
+    insts = _mixed(1)
+    b = ace.Batch(insts)
+    rng = np.random.default_rng(9)
+    phi0 = [rng.uniform(-0.9, 0.9, shp) for shp in b.shapes]
+    outs = []
+    for lim in (0, 1000, 8000):
+        b.set_resident_limit(lim)
+        b.set_all(phi0)
+        b.step(17)
+        outs.append(b.get_all())
+    for o in outs[1:]:
+        for x, y in zip(o, outs[0]):
+            assert np.array_equal(x, y)
+    rec = b.autotune(5)
+    assert '"choice"' in rec
+    b.set_all(phi0)
+    b.step(17)
+    for x, y in zip(b.get_all(), outs[0]):
+        assert np.array_equal(x, y)
+
+
+def test_batch_repeated_steps_and_rejects_bad_instances(ace):
+    insts = _mixed(2)[:10]
+    b = ace.Batch(insts)
+    rng = np.random.default_rng(4)
+    phi0 = [rng.uniform(-0.9, 0.9, shp) for shp in b.shapes]
+    b.set_all(phi0)
+    b.step(10)
+    b.step(10)
+    two = b.get_all()
+    b.set_all(phi0)
+    b.step(20)
+    for x, y in zip(b.get_all(), two):
+        assert np.array_equal(x, y)
+    bad = list(insts) + [(3, [8] * 3, [0] * 3, [1] * 3, 0.1, 1e-3, 0)]
+    with pytest.raises(ace.AceError):
+        ace.Batch(bad)
+
+
+@pytest.mark.timeout(900)
+def test_batch_workload_4096(ace, orc):
+    """The 4096-instance workload, 500 steps in one launch: every instance
+    equals its single-instance ace_step run bit for bit, and a sample of 96
+    instances across all classes matches the oracle."""
+    from paper_2312_07010_amd import inputs
+    descs = inputs.batch_instances()
+    insts = [(x.d, [x.N] * x.d, [0.0] * x.d, [1.0] * x.d, x.eps, x.dt, x.bc) for x in descs]
+    b = ace.Batch(insts)
+    assert all(s == 0 for s in b.status)
+    phi0 = [inputs.batch_phi0(i, shp) for i, shp in enumerate(b.shapes)]
+    b.set_all(phi0)
+    b.step(500)
+    got = b.get_all()
+    E, mx = b.monitor()
+    assert np.all(mx <= 1.0 + 4 * 2.0 ** -53)
+    for i, inst in enumerate(insts):
+        s = ace.Solver(*inst)
+        s.set_phi0(phi0[i])
+        s.step(500)
+        assert np.array_equal(s.get_phi(), got[i]), i
+        s.close()
+    order = np.argsort([t for t in b.totals])
+    sample = sorted(set(list(order[:24]) + list(order[-24:]) +
+                        list(np.random.default_rng(0).choice(len(insts), 48, replace=False))))
+    worst = 0.0
+    for i in sample:
+        p = orc.Problem(*insts[i])
+        want, Ew, _ = p.run(phi0[i], 500, 500)
+        worst = max(worst, float(np.abs(got[i] - want).max()))
+        assert E[i] == pytest.approx(Ew[-1], rel=1e-12)
+    print(f"batch 4096: max |phi - oracle| over {len(sample)} sampled instances = {worst:.3e}")
+    assert worst <= 1e-12
