@@ -76,7 +76,7 @@ def adjoint_ratio(ace, torch):
     phi0 = torch.tensor(inputs.uniform_field(s.shape, w.lo, w.hi, w.seed), device="cuda")
     tgt = torch.tensor(inputs.uniform_field(s.shape, w.lo, w.hi, w.extra["target_seed"]),
                        device="cuda")
-    s.forward_ckpt(phi0, 50, 32)
+    s.forward_ckpt(phi0, w.steps, w.extra["ckpt_every"])  # warm-up, same sizes
     s.backward(torch.zeros_like(phi0))
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -17,10 +17,17 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// mu = lambda R'(xi) = lambda / (1 + h (3 p1^2 - 1)), p1 = phi^{n+1}.  The
+// denominator lies in [1 - h, 1 + 2h]; its reciprocal is the hardware estimate
+// refined by two Newton-Raphson steps (quadratic convergence takes the
+// estimate's error below double rounding).
 __device__ __forceinline__ double mu_of(double lam, double p1, const StepCoef &c)
 {
-    // 1 + h (3 p1^2 - 1) = (1 - h) + 3 h p1^2
-    return lam / fma(c.h3, p1 * p1, c.omh);
+    const double dp = fma(c.h3, p1 * p1, c.omh);
+    double r = __builtin_amdgcn_rcp(dp);
+    r = fma(r, fma(-dp, r, 1.0), r);
+    r = fma(r, fma(-dp, r, 1.0), r);
+    return lam * r;
 }
 
 template <int D, int BC>

@@ -728,6 +728,10 @@ int ace_forward_ckpt(ace_solver *s, const double *phi0, int where, int64_t nstep
     const int64_t total = s->p.total;
     const int64_t nck = nsteps == 0 ? 1 : (nsteps + every - 1) / every;
     ACE_TRY(grow(&s->ckpt, &s->ckpt_cap, nck * total));
+    // size the reverse sweep's buffers now so ace_backward allocates nothing
+    ACE_TRY(grow(&s->seg, &s->seg_cap, (every + 1) * total));
+    ACE_TRY(grow(&s->lam, &s->lam_cap, 2 * total));
+    ACE_TRY(grow(&s->gpart, &s->gpart_cap, adjoint_partials_needed(s->shape) * every));
     const size_t bytes = (size_t)total * sizeof(double);
     for (int64_t j = 0; j < nck; ++j) {
         ACE_HIP(hipMemcpyAsync(s->ckpt + j * total, s->buf[s->cur], bytes, hipMemcpyDeviceToDevice,
