@@ -242,6 +242,31 @@ def test_linear_fourier_mode_amplification(orc, d, bc):
         np.testing.assert_allclose(phi1[big] / phi0[big], g, rtol=1e-9)
 
 
+@pytest.mark.parametrize("bc", [0, 1, 2])
+def test_node_coordinates_carry_the_eigenvectors(orc, bc):
+    """The node positions of Sec. 2 (HN: L + (i - 1/2) dx, HD: L + i dx for
+    i = 1..N-1, P: L + i dx for i = 0..N-1) are those at which the continuous
+    Laplacian eigenfunctions of each BC sample to the eigenvectors of the
+    printed D: cos(pi k (x - L + dx) / (M dx)) for Neumann (walls a node
+    beyond the ends), sin(pi k (x - L) / X) for Dirichlet, cos(2 pi k (x - L)
+    / X) for periodic."""
+    N, L, R = 16, -0.7, 1.3
+    p = orc.Problem(1, [N], [L], [R], 0.05, 0.01, bc)
+    x = p.coords(0)
+    X, M, dx = R - L, p.M[0], p.dx
+    D = dense_D(M, bc)
+    for k in (1, 3, 5):
+        if bc == 0:
+            v = np.cos(np.pi * k * (x - L + dx) / (M * dx))
+        elif bc == 1:
+            v = np.sin(np.pi * k * (x - L) / X)
+        else:
+            v = np.cos(2 * np.pi * k * (x - L) / X)
+        Dv = D @ v
+        lam = Dv @ v / (v @ v)
+        np.testing.assert_allclose(Dv, lam * v, atol=1e-12)
+
+
 # ---------------------------------------------------------------------------
 # Theorems 2 and 3: maximum principle and energy decay
 # ---------------------------------------------------------------------------
