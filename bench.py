@@ -149,6 +149,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--kernel", default="auto", choices=["auto", "march", "tblock", "direct"],
                     help="step kernel (auto = the library's choice)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the library's autotuner (kernel and plane-chunk choice)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="REPS",
                     help="only copy a 1 GiB device buffer REPS times (a plain copy kernel of "
                          "known size, for scaling HBM counters) and report its bandwidth")
@@ -196,7 +198,15 @@ def main():
     print(f"[bench] {w.name}: shape {s.shape}, params {s.params['kappa']:.7g} kappa, "
           f"{s.params['newton_iters']} Newton steps", file=sys.stderr, flush=True)
 
-    # warmup (also JIT-loads every kernel variant used below)
+    tuning = None
+    if args.kernel == "auto" and not args.no_autotune:
+        tuning = json.loads(s.autotune(20))
+        kernel, per_launch = s.get_kernel()
+        kname = {ace.ACE_KERNEL_MARCH: "k_march3d", ace.ACE_KERNEL_TBLOCK: "k_tblock3d",
+                 ace.ACE_KERNEL_DIRECT: "k_step_direct"}.get(kernel, str(kernel))
+        print(f"[bench] autotuner choice: {tuning['choice']}", file=sys.stderr, flush=True)
+    # warmup (also loads every kernel variant used below)
+    s.set_phi0(phi0_dev)
     s.run_monitored(args.warmup, args.every)
     torch.cuda.synchronize()
 
@@ -251,6 +261,8 @@ def main():
                    "nodes": int(n), "monitor_every": args.every},
         "roofline": roof,
     }
+    if tuning is not None:
+        out["autotune"] = tuning["choice"]
     s.close()
     del phi0_dev
     torch.cuda.empty_cache()

@@ -640,7 +640,7 @@ int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap)
     if (s->p.total <= RESIDENT_MAX) cands.push_back({ACE_KERNEL_RESIDENT, s->zchunk});
     if (march_supported(s->shape)) cands.push_back({ACE_KERNEL_MARCH, s->zchunk});
     if (tblock_supported(s->shape))
-        for (int zc : {16, 32, 64, 128})
+        for (int zc : {16, 24, 32, 40, 48, 64, 128})
             if (zc <= std::max<int64_t>(s->shape.M0, 16)) cands.push_back({ACE_KERNEL_TBLOCK, zc});
     const int64_t total = s->p.total;
     double *save = nullptr;

@@ -59,6 +59,36 @@ __device__ __forceinline__ double cubic_root(double xi, const StepCoef &c)
     return copysign(x, xi);
 }
 
+// Same root with the Newton count fixed at compile time (NIT > 0; the
+// iteration and hence every rounding is identical to cubic_root with
+// c.nit == NIT), so the loop unrolls and its constants stay in registers.
+template <int NIT>
+__device__ __forceinline__ double cubic_root_n(double xi, const StepCoef &c)
+{
+    if (NIT <= 0) return cubic_root(xi, c);
+    const double a = fabs(xi);
+    double x = fma(c.h * a, fma(-a, a, 1.0), a);
+    if (a > 1.0 || c.h > 0.5) x = a;
+#pragma unroll
+    for (int k = 0; k < (NIT > 0 ? NIT : 1); ++k) {
+        const double x2 = x * x;
+        const double p = fma(c.h, fma(x, x2, -x), x - a);
+        const double dp = fma(c.h3, x2, c.omh);
+        x = fma(-p, approx_rcp(dp), x);
+    }
+    if (a > 1.0) {
+        for (int k = 0; k < 200; ++k) {
+            const double x2 = x * x;
+            const double p = fma(c.h, fma(x, x2, -x), x - a);
+            const double dp = fma(c.h3, x2, c.omh);
+            const double step = p / dp;
+            x -= step;
+            if (!(fabs(step) > 0x1p-54 * x)) break;
+        }
+    }
+    return copysign(x, xi);
+}
+
 // Explicit part xi from the node value p and the sum over axes of its two
 // neighbours' sum (nsum = sum_k (p_{+k} + p_{-k})), for d = D.
 template <int D>
@@ -74,6 +104,12 @@ template <int D>
 __device__ __forceinline__ double update(double p, double nsum, const StepCoef &c)
 {
     return cubic_root(explicit_part<D>(p, nsum, c), c);
+}
+
+template <int D, int NIT>
+__device__ __forceinline__ double update_n(double p, double nsum, const StepCoef &c)
+{
+    return cubic_root_n<NIT>(explicit_part<D>(p, nsum, c), c);
 }
 
 // Value used for an out-of-range neighbour (rows of the paper's D matrices):

@@ -71,7 +71,7 @@ __device__ __forceinline__ double load_at2(const double *__restrict__ in, int64_
     return (base < 0 || off < 0) ? 0.0 : in[base + off];
 }
 
-template <int BC, bool MON>
+template <int BC, bool MON, int NIT>
 __global__ __launch_bounds__(NT) void k_tblock3d(Shape s, StepCoef c, const double *__restrict__ in,
                                                  double *__restrict__ out,
                                                  double *__restrict__ partials, int tiles_x,
@@ -150,7 +150,10 @@ __global__ __launch_bounds__(NT) void k_tblock3d(Shape s, StepCoef c, const doub
     for (int r = 0; r < RYT; ++r) L0[own[r]] = q1[r];
     __syncthreads();
 
-    // level-1 queue: w0 = plane zc-2, w1 = zc-1, w2 = zc
+    // level-1 queue (plane zc-2, zc-1, zc) and the march.  The body below is
+    // written once against named queue slots; the loop calls it with the
+    // slots rotated (period 4 for level 0, 3 for level 1, so 12 calls per
+    // turn), which replaces the queue shifts by register renaming.
     double w0[RYT], w1[RYT], w2[RYT];
 #pragma unroll
     for (int r = 0; r < RYT; ++r) {
@@ -161,25 +164,35 @@ __global__ __launch_bounds__(NT) void k_tblock3d(Shape s, StepCoef c, const doub
     MonAcc m;
     mon_zero(m);
     int bl0 = 0, bl1 = 0;
-    for (int64_t zc = z0 - 1;; ++zc) {
+    int64_t zc = z0 - 1;
+    // rows a wavefront can skip: level 1 is needed on region rows 1..RH-2,
+    // level 2 on the tile rows 2..RH-3 (a wavefront is one thread row, so
+    // these tests are uniform across it)
+    auto need1 = [&](int r) { const int ry = tr * RYT + r; return ry >= 1 && ry < RH - 1; };
+    auto need2 = [&](int r) { const int ry = tr * RYT + r; return ry >= 2 && ry < RH - 2; };
+
+    auto body = [&](double(&Q0)[RYT], double(&Q1)[RYT], double(&Q2)[RYT], double(&Q3)[RYT],
+                    double(&W0)[RYT], double(&W1)[RYT], double(&W2)[RYT]) __attribute__((always_inline)) {
+        // Q0..Q3: level-0 planes zc-1..zc+2; W0, W1: level-1 planes zc-2, zc-1
         const double *l0 = L0 + bl0 * LP;
         double *l1w = L1 + bl1 * LP;
         const double *l1r = L1 + (bl1 ^ 1) * LP;
-        // --- A: level 1 of plane zc on the whole region ---
+        // --- A: level 1 of plane zc on the region ---
         const bool mon_plane = MON && zc >= z0 && zc < z1;
 #pragma unroll
         for (int r = 0; r < RYT; ++r) {
-            const double p = q1[r];
+            if (!need1(r)) continue;
+            const double p = Q1[r];
             const double xm = l0[own[r] - 1];
             const double xp = l0[own[r] + 1];
-            const double ym = (r > 0) ? q1[r > 0 ? r - 1 : 0] : l0[own[r] - LW];
-            const double yp = (r < RYT - 1) ? q1[r < RYT - 1 ? r + 1 : 0] : l0[own[r] + LW];
-            const double nsum = ((q0[r] + q2[r]) + (ym + yp)) + (xm + xp);
-            const double v = update<3>(p, nsum, c);
-            w2[r] = v;
+            const double ym = (r > 0) ? Q1[r > 0 ? r - 1 : 0] : l0[own[r] - LW];
+            const double yp = (r < RYT - 1) ? Q1[r < RYT - 1 ? r + 1 : 0] : l0[own[r] + LW];
+            const double nsum = ((Q0[r] + Q2[r]) + (ym + yp)) + (xm + xp);
+            const double v = update_n<3, NIT>(p, nsum, c);
+            W2[r] = v;
             l1w[own[r]] = v;
             if (mon_plane && oof[r] >= 0) {
-                const double dz = q2[r] - p, dy = yp - p, dx = xp - p;
+                const double dz = Q2[r] - p, dy = yp - p, dx = xp - p;
                 double g = fma(dz, dz, fma(dy, dy, dx * dx));
                 if (BC == BC_HD) {
                     if (zc == 0) g = fma(p, p, g);
@@ -197,8 +210,9 @@ __global__ __launch_bounds__(NT) void k_tblock3d(Shape s, StepCoef c, const doub
             double *const orow = out + zo * PS;
 #pragma unroll
             for (int r = 0; r < RYT; ++r) {
-                const double p = w1[r];
-                double zm = w0[r], zp = w2[r];
+                if (!need2(r)) continue;
+                const double p = W1[r];
+                double zm = W0[r], zp = W2[r];
                 if (BC != BC_P) {
                     if (zo == 0) zm = (BC == BC_HN) ? p : 0.0;
                     if (zo == s.M0 - 1) zp = (BC == BC_HN) ? p : 0.0;
@@ -208,27 +222,40 @@ __global__ __launch_bounds__(NT) void k_tblock3d(Shape s, StepCoef c, const doub
                 const double ym = l1r[nym[r]];
                 const double yp = l1r[nyp[r]];
                 const double nsum = ((zm + zp) + (ym + yp)) + (xm + xp);
-                const double v = update<3>(p, nsum, c);
+                const double v = update_n<3, NIT>(p, nsum, c);
                 if (oof[r] >= 0) orow[oof[r]] = v;
             }
         }
-        if (zc >= z1) break;
-        // --- advance both queues, stage level-0 plane zc+1 ---
+        if (zc >= z1) return true;
+        // --- next level-0 plane zc+3 into the dead slot Q0; stage plane zc+1 ---
         const int64_t bn = (zc + 3 <= z1 + 1) ? plane_base2<BC>(s, zc + 3) : -1;
 #pragma unroll
-        for (int r = 0; r < RYT; ++r) {
-            w0[r] = w1[r];
-            w1[r] = w2[r];
-            q0[r] = q1[r];
-            q1[r] = q2[r];
-            q2[r] = q3[r];
-            q3[r] = load_at2(in, bn, off[r]);
-        }
+        for (int r = 0; r < RYT; ++r) Q0[r] = load_at2(in, bn, off[r]);
         bl0 ^= 1;
         bl1 ^= 1;
 #pragma unroll
-        for (int r = 0; r < RYT; ++r) L0[bl0 * LP + own[r]] = q1[r];
+        for (int r = 0; r < RYT; ++r) L0[bl0 * LP + own[r]] = Q2[r];
         __syncthreads();
+        ++zc;
+        return false;
+    };
+    double(&qa)[RYT] = q0;
+    double(&qb)[RYT] = q1;
+    double(&qc)[RYT] = q2;
+    double(&qd)[RYT] = q3;
+    for (;;) {
+        if (body(qa, qb, qc, qd, w0, w1, w2)) break;
+        if (body(qb, qc, qd, qa, w1, w2, w0)) break;
+        if (body(qc, qd, qa, qb, w2, w0, w1)) break;
+        if (body(qd, qa, qb, qc, w0, w1, w2)) break;
+        if (body(qa, qb, qc, qd, w1, w2, w0)) break;
+        if (body(qb, qc, qd, qa, w2, w0, w1)) break;
+        if (body(qc, qd, qa, qb, w0, w1, w2)) break;
+        if (body(qd, qa, qb, qc, w1, w2, w0)) break;
+        if (body(qa, qb, qc, qd, w2, w0, w1)) break;
+        if (body(qb, qc, qd, qa, w0, w1, w2)) break;
+        if (body(qc, qd, qa, qb, w1, w2, w0)) break;
+        if (body(qd, qa, qb, qc, w2, w0, w1)) break;
     }
     if (MON) block_reduce_store(m, red, partials + 3 * t);
 }
@@ -254,18 +281,24 @@ hipError_t launch_step_tblock2(const Shape &s, const StepCoef &c, const double *
     const int nchunks = (int)((s.M0 + zchunk - 1) / zchunk);
     const int64_t nblk = (int64_t)tiles_x * tiles_y * nchunks;
     if (nparts) *nparts = nblk;
-#define ACE_TB(BB)                                                                              \
-    if (s.bc == BB) {                                                                           \
-        if (partials)                                                                           \
-            hipLaunchKernelGGL((k_tblock3d<BB, true>), dim3((unsigned)nblk), dim3(NT), 0, st, s, \
-                               c, in, out, partials, tiles_x, tiles_y, zchunk);                 \
-        else                                                                                    \
-            hipLaunchKernelGGL((k_tblock3d<BB, false>), dim3((unsigned)nblk), dim3(NT), 0, st,   \
-                               s, c, in, out, partials, tiles_x, tiles_y, zchunk);              \
-        return hipGetLastError();                                                               \
+#define ACE_TB_N(BB, NN)                                                                        \
+    if (partials)                                                                               \
+        hipLaunchKernelGGL((k_tblock3d<BB, true, NN>), dim3((unsigned)nblk), dim3(NT), 0, st, s,  \
+                           c, in, out, partials, tiles_x, tiles_y, zchunk);                     \
+    else                                                                                        \
+        hipLaunchKernelGGL((k_tblock3d<BB, false, NN>), dim3((unsigned)nblk), dim3(NT), 0, st,   \
+                           s, c, in, out, partials, tiles_x, tiles_y, zchunk);                  \
+    return hipGetLastError();
+#define ACE_TB(BB)                                        \
+    if (s.bc == BB) {                                     \
+        if (c.nit == 1) { ACE_TB_N(BB, 1) }               \
+        if (c.nit == 2) { ACE_TB_N(BB, 2) }               \
+        if (c.nit == 3) { ACE_TB_N(BB, 3) }               \
+        ACE_TB_N(BB, 0)                                   \
     }
     ACE_TB(BC_HN) ACE_TB(BC_HD) ACE_TB(BC_P)
 #undef ACE_TB
+#undef ACE_TB_N
     return hipErrorInvalidValue;
 }
 
