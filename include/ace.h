@@ -121,6 +121,13 @@ int ace_bind_fields(ace_solver *s, double *a, double *b);
  * trained.  Errors: ACE_E_ARG.  Warning: ACE_W_CONDITIONS. */
 int ace_set_eps(ace_solver *s, double eps);
 
+/* Runs of ace_step longer than twice `launches` launches are replayed from a
+ * HIP graph holding `launches` step launches (rounded up to even), captured
+ * on first use for the handle's current buffers and kernel; 0 disables graph
+ * replay (every launch is issued directly).  Default 32.  Results are
+ * identical either way. */
+int ace_set_graph_launches(ace_solver *s, int64_t launches);
+
 /* Kernel choice for ace_step (ACE_KERNEL_*) and its temporal depth (steps
  * per launch; 0 = default; ACE_KERNEL_TBLOCK accepts 0 or 2).  A choice that
  * does not apply to the handle's dimension or size falls back to

@@ -68,6 +68,7 @@ _SIGS = {
     "ace_bind_fields": (ctypes.c_int, [_vp, _vp, _vp]),
     "ace_set_kernel": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
     "ace_set_eps": (ctypes.c_int, [_vp, _dbl]),
+    "ace_set_graph_launches": (ctypes.c_int, [_vp, _i64]),
     "ace_get_kernel": (ctypes.c_int, [_vp, _P(ctypes.c_int), _P(ctypes.c_int)]),
     "ace_set_phi0": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
     "ace_step": (ctypes.c_int, [_vp, _i64]),
@@ -206,6 +207,9 @@ class Solver:
     def set_eps(self, eps):
         self.last_status = _check(lib().ace_set_eps(self._h, float(eps)), "ace_set_eps")
         return self.last_status
+
+    def set_graph_launches(self, launches):
+        _check(lib().ace_set_graph_launches(self._h, int(launches)), "ace_set_graph_launches")
 
     def set_kernel(self, kernel, depth=0):
         _check(lib().ace_set_kernel(self._h, int(kernel), int(depth)), "ace_set_kernel")

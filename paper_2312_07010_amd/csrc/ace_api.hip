@@ -223,6 +223,16 @@ struct ace_solver {
     int64_t gpart_cap = 0;
     double *gsum = nullptr;
     int64_t field_version = 0;
+    // graph replay of runs of launches (0 disables)
+    int64_t graph_launches = 32;
+    hipStream_t capture = nullptr;
+    struct GraphEntry {
+        int kernel, zchunk, cur;
+        const double *b0, *b1;
+        hipGraph_t g;
+        hipGraphExec_t e;
+    };
+    std::vector<GraphEntry> graphs;
 };
 
 namespace {
@@ -267,6 +277,58 @@ int launch_steps(ace_solver *s, int kernel, int64_t remaining, bool want_mon, in
     return taken;
 }
 
+void drop_graphs(ace_solver *s)
+{
+    for (auto &g : s->graphs) {
+        (void)hipGraphExecDestroy(g.e);
+        (void)hipGraphDestroy(g.g);
+    }
+    s->graphs.clear();
+}
+
+// Graph of s->graph_launches launches (an even count, so the field returns to
+// the same buffer) of `kernel` starting from buf[cur]; captured once on a
+// private stream and replayed on the handle's stream.  Kernel nodes only.
+int graph_for(ace_solver *s, int kernel, hipGraphExec_t *out)
+{
+    for (auto &g : s->graphs)
+        if (g.kernel == kernel && g.zchunk == s->zchunk && g.cur == s->cur && g.b0 == s->buf[0] &&
+            g.b1 == s->buf[1]) {
+            *out = g.e;
+            return ACE_OK;
+        }
+    if (!s->capture) ACE_HIP(hipStreamCreateWithFlags(&s->capture, hipStreamNonBlocking));
+    const hipStream_t user = s->stream;
+    const int cur0 = s->cur;
+    const int64_t steps0 = s->steps;
+    s->stream = s->capture;
+    ACE_HIP(hipStreamBeginCapture(s->capture, hipStreamCaptureModeThreadLocal));
+    int rc = ACE_OK;
+    for (int64_t i = 0; i < s->graph_launches && rc >= 0; ++i) {
+        const int t = launch_steps(s, kernel, kernel == ACE_KERNEL_TBLOCK ? 2 : 1, false, nullptr);
+        if (t < 0) rc = t;
+    }
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(s->capture, &g);
+    s->stream = user;
+    s->cur = cur0;
+    s->steps = steps0;
+    if (rc < 0) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    ACE_HIP(ce);
+    hipGraphExec_t e = nullptr;
+    hipError_t ie = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_status(ie);
+    }
+    s->graphs.push_back({kernel, s->zchunk, cur0, s->buf[0], s->buf[1], g, e});
+    *out = e;
+    return ACE_OK;
+}
+
 int advance(ace_solver *s, int64_t nsteps)
 {
     if (nsteps <= 0) return ACE_OK;
@@ -276,7 +338,19 @@ int advance(ace_solver *s, int64_t nsteps)
         s->steps += nsteps;
         return ACE_OK;
     }
-    for (int64_t i = 0; i < nsteps;) {
+    const int per = (k == ACE_KERNEL_TBLOCK) ? 2 : 1;
+    int64_t i = 0;
+    if (s->graph_launches >= 2) {
+        const int64_t chunk = s->graph_launches * per;
+        while (nsteps - i >= 2 * chunk) {
+            hipGraphExec_t e = nullptr;
+            ACE_TRY(graph_for(s, k, &e));
+            ACE_HIP(hipGraphLaunch(e, s->stream));
+            s->steps += chunk;  // even launch count: s->cur is unchanged
+            i += chunk;
+        }
+    }
+    while (i < nsteps) {
         const int t = launch_steps(s, k, nsteps - i, false, nullptr);
         if (t < 0) return t;
         i += t;
@@ -403,6 +477,8 @@ int ace_create(int d, const int64_t *N, const double *L, const double *R, double
 int ace_destroy(ace_solver *s)
 {
     if (!s) return ACE_E_ARG;
+    drop_graphs(s);
+    if (s->capture) (void)hipStreamDestroy(s->capture);
     for (int i = 0; i < 2; ++i)
         if (s->own[i]) (void)hipFree(s->own[i]);
     double *devs[] = {s->partials, s->mon, s->ckpt, s->seg, s->lam, s->gpart, s->gsum};
@@ -482,6 +558,15 @@ int ace_bind_fields(ace_solver *s, double *a, double *b)
     s->cur = 0;
     s->steps = 0;
     s->field_version++;
+    drop_graphs(s);
+    return ACE_OK;
+}
+
+int ace_set_graph_launches(ace_solver *s, int64_t launches)
+{
+    if (!s || launches < 0) return ACE_E_ARG;
+    s->graph_launches = launches + (launches & 1);  // even: the buffer parity returns
+    drop_graphs(s);
     return ACE_OK;
 }
 
@@ -494,6 +579,7 @@ int ace_set_eps(ace_solver *s, double eps)
     s->p = q;
     s->coef = coef_of(q);
     s->ck_count = 0;  // checkpoints of the old eps are no longer valid
+    drop_graphs(s);   // captured launches carry the old coefficients
     return rc;
 }
 

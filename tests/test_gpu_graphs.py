@@ -1,0 +1,66 @@
+"""Graph replay of step runs: every replay must equal the same steps issued
+directly, with the program's own eager work and synchronisations between the
+replays (the graphs hold kernel launches only)."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ace():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2312_07010_amd import ace as A
+    A.lib()
+    return A
+
+
+@pytest.mark.parametrize("d,N,bc,kernel", [(2, 200, 0, 1), (2, 130, 2, 1), (3, 40, 1, 2),
+                                           (3, 45, 2, 4), (1, 9000, 1, 1)])
+def test_graph_replays_match_direct_launches(ace, d, N, bc, kernel):
+    dt = 1e-3
+    dx = 1.0 / N
+    eps = math.sqrt(0.1 / d * dx * dx / dt)
+    args = (d, [N] * d, [0.0] * d, [1.0] * d, eps, dt, bc)
+    eager = ace.Solver(*args)
+    eager.set_kernel(kernel)
+    eager.set_graph_launches(0)
+    graph = ace.Solver(*args)
+    graph.set_kernel(kernel)
+    graph.set_graph_launches(4)
+    rng = np.random.default_rng(N)
+    phi0 = rng.uniform(-0.9, 0.9, eager.shape)
+    eager.set_phi0(phi0)
+    graph.set_phi0(phi0)
+    for rep in range(4):
+        n = 37 + 16 * rep  # several replays of the 4-launch graph per call, plus a tail
+        eager.step(n)
+        graph.step(n)
+        a = eager.get_phi()
+        b = graph.get_phi()
+        assert np.array_equal(a, b), rep
+        # eager work between replays: monitors and a field reset
+        assert graph.energy() == eager.energy()
+        if rep == 1:
+            eager.set_phi0(a[::-1].copy() if d == 1 else a.T.copy())
+            graph.set_phi0(a[::-1].copy() if d == 1 else a.T.copy())
+    assert graph.step_count == eager.step_count
+
+
+def test_graph_dropped_when_eps_changes(ace):
+    args = (2, [100, 100], [0, 0], [1, 1], 0.01, 1e-3, 0)
+    a = ace.Solver(*args)
+    b = ace.Solver(*args)
+    a.set_graph_launches(0)
+    b.set_graph_launches(2)
+    phi0 = np.random.default_rng(1).uniform(-0.9, 0.9, a.shape)
+    for s in (a, b):
+        s.set_phi0(phi0)
+        s.step(20)
+        s.set_eps(0.013)
+        s.step(20)
+    assert np.array_equal(a.get_phi(), b.get_phi())
