@@ -184,6 +184,31 @@ void oracle_step(int d, const long *M, int bc, double kappa, double h,
         out[i] = oracle_root(explicit_part(phi, d, M, st, bc, kappa, h, i), h);
 }
 
+/* The fully explicit comparison scheme of Sec. 3.3, Remark 2 (FEX-FD):
+ * forward Euler in time with the same central Laplacian, all of f explicit,
+ *   phi^{n+1} = phi + kappa * sum_k (phi_{+k} + phi_{-k} - 2 phi) - dt f(phi).
+ * (The paper states only its step condition dt <= (1 - 2 d kappa)/2; this
+ * is the standard scheme that condition belongs to.)                       */
+void oracle_step_fex(int d, const long *M, int bc, double kappa, double dt,
+                     const double *phi, double *out)
+{
+    long st[3];
+    strides(d, M, st);
+    const long n = oracle_total(d, M);
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) {
+        const double p = phi[i];
+        double lap = 0.0;
+        for (int k = 0; k < d; ++k) {
+            const double lo = neighbour(phi, d, M, st, bc, i, k, -1);
+            const double hi = neighbour(phi, d, M, st, bc, i, k, +1);
+            lap = lap + (hi + lo - 2.0 * p);
+        }
+        const double fp = p * p * p - p;
+        out[i] = p + kappa * lap - dt * fp;
+    }
+}
+
 /* ---------------------------------------------------------------------- */
 /* Monitors (Sec. 3.2 maximum norm, Sec. 3.3 Theorem 3 discrete energy)    */
 /* ---------------------------------------------------------------------- */
@@ -271,9 +296,21 @@ double oracle_maxnorm(long n, const double *phi)
 /* Advance phi in place by nsteps.  If every > 0, E[j] and maxn[j] receive
  * the monitors at steps 0, every, 2*every, ... <= nsteps (arrays of length
  * nsteps/every + 1).  Returns 0, or -1 when scratch memory is missing.    */
+int oracle_run_scheme(int d, const long *M, int bc, double kappa, double dt,
+                      double dx, double *phi, long nsteps, long every, double *E,
+                      double *maxn, int scheme);
+
 int oracle_run(int d, const long *M, int bc, double kappa, double dt,
                double dx, double *phi, long nsteps, long every, double *E,
                double *maxn)
+{
+    return oracle_run_scheme(d, M, bc, kappa, dt, dx, phi, nsteps, every, E, maxn, 0);
+}
+
+/* scheme 0: the RLB-MIE-FD step; scheme 1: FEX-FD (Remark 2).           */
+int oracle_run_scheme(int d, const long *M, int bc, double kappa, double dt,
+                      double dx, double *phi, long nsteps, long every, double *E,
+                      double *maxn, int scheme)
 {
     const long n = oracle_total(d, M);
     const double h = 0.5 * dt;
@@ -288,7 +325,8 @@ int oracle_run(int d, const long *M, int bc, double kappa, double dt,
             ++j;
         }
         if (s == nsteps) break;
-        oracle_step(d, M, bc, kappa, h, cur, nxt);
+        if (scheme == 1) oracle_step_fex(d, M, bc, kappa, dt, cur, nxt);
+        else oracle_step(d, M, bc, kappa, h, cur, nxt);
         double *t = cur;
         cur = nxt;
         nxt = t;

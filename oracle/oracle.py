@@ -52,6 +52,11 @@ def lib():
         L.oracle_run.argtypes = [ctypes.c_int, _L, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, _D, ctypes.c_long, ctypes.c_long, _D, _D]
         L.oracle_run.restype = ctypes.c_int
+        L.oracle_step_fex.argtypes = [ctypes.c_int, _L, ctypes.c_int, ctypes.c_double, ctypes.c_double, _D, _D]
+        L.oracle_step_fex.restype = None
+        L.oracle_run_scheme.argtypes = [ctypes.c_int, _L, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, _D, ctypes.c_long, ctypes.c_long, _D, _D, ctypes.c_int]
+        L.oracle_run_scheme.restype = ctypes.c_int
         L.oracle_adjoint.argtypes = [ctypes.c_int, _L, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                      _D, ctypes.c_long, _D, _D, _D]
         L.oracle_adjoint.restype = ctypes.c_int
@@ -82,7 +87,7 @@ def root(xi, h):
 class Problem:
     """One Allen-Cahn problem: d, N[], L[], R[], eps, dt, bc (Sec. 2)."""
 
-    def __init__(self, d, N, L, R, eps, dt, bc):
+    def __init__(self, d, N, L, R, eps, dt, bc, scheme=0):
         self.d = int(d)
         self.N = [int(n) for n in N][: self.d]
         self.L = [float(x) for x in L][: self.d]
@@ -97,11 +102,15 @@ class Problem:
         self.M = [int(lib().oracle_nodes_per_axis(n, self.bc)) for n in self.N]
         self.shape = tuple(self.M)
         self._Marr = (ctypes.c_long * 3)(*(self.M + [1] * (3 - self.d)))
+        self.scheme = int(scheme)  # 0: RLB-MIE-FD, 1: FEX-FD (Remark 2)
 
-    # Theorem 2 hypothesis on the step: dt <= 1 - 2 d kappa, 0 < kappa < 1/(2d)
+    # Theorem 2 hypothesis on the step: dt <= 1 - 2 d kappa, 0 < kappa < 1/(2d);
+    # for FEX-FD Remark 2's dt <= (1 - 2 d kappa) / 2
     def conditions_ok(self, rel=1e-12):
-        return (self.dt <= (1.0 - 2 * self.d * self.kappa) * (1.0 + rel)
-                and 0.0 < self.kappa < 1.0 / (2 * self.d))
+        bound = 1.0 - 2 * self.d * self.kappa
+        if self.scheme == 1:
+            bound *= 0.5
+        return self.dt <= bound * (1.0 + rel) and 0.0 < self.kappa < 1.0 / (2 * self.d)
 
     def coords(self, axis):
         return np.array([lib().oracle_node_coord(self.bc, self.L[axis], self.dx, i)
@@ -116,7 +125,10 @@ class Problem:
     def step(self, phi):
         phi = _f64(phi).reshape(self.shape)
         out = np.empty_like(phi)
-        lib().oracle_step(self.d, self._Marr, self.bc, self.kappa, self.h, _dp(phi), _dp(out))
+        if self.scheme == 1:
+            lib().oracle_step_fex(self.d, self._Marr, self.bc, self.kappa, self.dt, _dp(phi), _dp(out))
+        else:
+            lib().oracle_step(self.d, self._Marr, self.bc, self.kappa, self.h, _dp(phi), _dp(out))
         return out
 
     def run(self, phi0, nsteps, every=0):
@@ -125,8 +137,8 @@ class Problem:
         nmon = nsteps // every + 1 if every > 0 else 0
         E = np.empty(max(nmon, 1))
         mx = np.empty(max(nmon, 1))
-        rc = lib().oracle_run(self.d, self._Marr, self.bc, self.kappa, self.dt, self.dx,
-                              _dp(phi), int(nsteps), int(every), _dp(E), _dp(mx))
+        rc = lib().oracle_run_scheme(self.d, self._Marr, self.bc, self.kappa, self.dt, self.dx,
+                                     _dp(phi), int(nsteps), int(every), _dp(E), _dp(mx), self.scheme)
         if rc != 0:
             raise MemoryError("oracle_run")
         return phi, E[:nmon], mx[:nmon]
