@@ -58,6 +58,10 @@ extern "C" {
 #define ACE_KERNEL_RESIDENT 3 /* whole field in LDS, many steps per launch    */
 #define ACE_KERNEL_TBLOCK 4  /* 3D: temporal blocking, 2 steps per launch      */
 
+/* ---- schemes (ace_set_scheme) ------------------------------------------ */
+#define ACE_SCHEME_RLB_MIE 0 /* the paper's scheme (default)                   */
+#define ACE_SCHEME_FEX 1     /* fully explicit comparison scheme (Remark 2)     */
+
 typedef struct ace_solver ace_solver;
 
 /* Derived parameters of a handle (Sec. 2 and Theorem 2 of Sec. 3.2). */
@@ -77,6 +81,7 @@ typedef struct {
     int conditions_ok;  /* 1 if dt <= (1 - 2 d kappa)(1 + 1e-12) and
                            0 < kappa < 1/(2d)                                 */
     int newton_iters;   /* Newton steps of the pointwise cubic solve         */
+    int scheme;         /* ACE_SCHEME_*                                      */
 } ace_params_t;
 
 /* ---- handle lifecycle --------------------------------------------------- */
@@ -127,6 +132,14 @@ int ace_set_eps(ace_solver *s, double eps);
  * replay (every launch is issued directly).  Default 32.  Results are
  * identical either way. */
 int ace_set_graph_launches(ace_solver *s, int64_t launches);
+
+/* Selects the time step.  ACE_SCHEME_RLB_MIE (default) is the paper's scheme.
+ * ACE_SCHEME_FEX is the fully explicit comparison scheme of Sec. 3.3,
+ * Remark 2, phi^{n+1} = phi + kappa sum_k (phi_{+k} + phi_{-k} - 2 phi)
+ * - dt f(phi), whose condition is dt <= (1 - 2 d kappa)/2; every kernel
+ * choice supports both.  The reverse sweep supports only ACE_SCHEME_RLB_MIE.
+ * Warning: ACE_W_CONDITIONS. */
+int ace_set_scheme(ace_solver *s, int scheme);
 
 /* Kernel choice for ace_step (ACE_KERNEL_*) and its temporal depth (steps
  * per launch; 0 = default; ACE_KERNEL_TBLOCK accepts 0 or 2).  A choice that
@@ -213,7 +226,7 @@ int ace_adjoint(ace_solver *s, const double *phi0, int64_t nsteps,
  * dphi0 and *deps2 (host).  Errors: ACE_E_STATE if no checkpoints exist or
  * the field was changed since ace_forward_ckpt. */
 int ace_forward_ckpt(ace_solver *s, const double *phi0, int where, int64_t nsteps,
-                     int64_t ckpt_every);
+                     int64_t ckpt_every);  /* ACE_E_STATE under ACE_SCHEME_FEX */
 int ace_backward(ace_solver *s, const double *lambdaT, double *dphi0, double *deps2,
                  int where);
 

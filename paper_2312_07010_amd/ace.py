@@ -23,6 +23,7 @@ BC = {"HN": ACE_BC_HN, "HD": ACE_BC_HD, "P": ACE_BC_P}
 ACE_HOST, ACE_DEVICE = 0, 1
 ACE_KERNEL_AUTO, ACE_KERNEL_DIRECT, ACE_KERNEL_MARCH = 0, 1, 2
 ACE_KERNEL_RESIDENT, ACE_KERNEL_TBLOCK = 3, 4
+ACE_SCHEME_RLB_MIE, ACE_SCHEME_FEX = 0, 1
 
 _i64 = ctypes.c_int64
 _dbl = ctypes.c_double
@@ -40,7 +41,8 @@ class Params(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int), ("bc", ctypes.c_int), ("N", _i64 * 3), ("M", _i64 * 3),
                 ("total", _i64), ("dx", _dbl), ("dt", _dbl), ("eps", _dbl), ("kappa", _dbl),
                 ("h", _dbl), ("dt_bound", _dbl), ("omega1", _dbl), ("s", _dbl),
-                ("conditions_ok", ctypes.c_int), ("newton_iters", ctypes.c_int)]
+                ("conditions_ok", ctypes.c_int), ("newton_iters", ctypes.c_int),
+                ("scheme", ctypes.c_int)]
 
     def as_dict(self):
         out = {}
@@ -68,6 +70,7 @@ _SIGS = {
     "ace_bind_fields": (ctypes.c_int, [_vp, _vp, _vp]),
     "ace_set_kernel": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
     "ace_set_eps": (ctypes.c_int, [_vp, _dbl]),
+    "ace_set_scheme": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ace_set_graph_launches": (ctypes.c_int, [_vp, _i64]),
     "ace_get_kernel": (ctypes.c_int, [_vp, _P(ctypes.c_int), _P(ctypes.c_int)]),
     "ace_set_phi0": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
@@ -206,6 +209,10 @@ class Solver:
 
     def set_eps(self, eps):
         self.last_status = _check(lib().ace_set_eps(self._h, float(eps)), "ace_set_eps")
+        return self.last_status
+
+    def set_scheme(self, scheme):
+        self.last_status = _check(lib().ace_set_scheme(self._h, int(scheme)), "ace_set_scheme")
         return self.last_status
 
     def set_graph_launches(self, launches):

@@ -72,6 +72,16 @@ int newton_iters_for(double h)
     return need;
 }
 
+// Theorem 2's step condition dt <= 1 - 2 d kappa, 0 < kappa < 1/(2d) (with
+// 1e-12 relative slack for the equality case); for the explicit comparison
+// scheme Remark 2's dt <= (1 - 2 d kappa)/2.
+void set_conditions(Problem &p)
+{
+    double bound = 1.0 - 2.0 * p.d * p.kappa;
+    if (p.scheme == ACE_SCHEME_FEX) bound *= 0.5;
+    p.cond_ok = (p.dt <= bound * (1.0 + 1e-12)) && p.kappa > 0.0 && p.kappa < 1.0 / (2.0 * p.d);
+}
+
 // Validates the ace_create arguments and fills the derived parameters.
 int derive(int d, const int64_t *N, const double *L, const double *R, double eps, double dt,
            int bc, Problem &p)
@@ -120,8 +130,8 @@ int derive(int d, const int64_t *N, const double *L, const double *R, double eps
     }
     p.total = total;
     p.nit = newton_iters_for(p.h);
-    p.cond_ok = (dt <= (1.0 - 2.0 * d * p.kappa) * (1.0 + 1e-12)) && p.kappa > 0.0 &&
-                p.kappa < 1.0 / (2.0 * d);
+    p.scheme = ACE_SCHEME_RLB_MIE;
+    set_conditions(p);
     return p.cond_ok ? ACE_OK : ACE_W_CONDITIONS;
 }
 
@@ -154,6 +164,8 @@ StepCoef coef_of(const Problem &p)
     c.omh = 1.0 - p.h;
     c.h3 = 3.0 * p.h;
     c.nit = p.nit;
+    c.fex = (p.scheme == ACE_SCHEME_FEX) ? 1 : 0;
+    c.dt = p.dt;
     return c;
 }
 
@@ -534,6 +546,7 @@ int ace_params(const ace_solver *s, ace_params_t *q)
     q->s = q->omega1 / p.kappa;
     q->conditions_ok = p.cond_ok;
     q->newton_iters = p.nit;
+    q->scheme = p.scheme;
     return ACE_OK;
 }
 
@@ -574,13 +587,27 @@ int ace_set_eps(ace_solver *s, double eps)
 {
     if (!s) return ACE_E_ARG;
     Problem q;
-    const int rc = derive(s->p.d, s->p.N, s->p.L, s->p.R, eps, s->p.dt, s->p.bc, q);
+    int rc = derive(s->p.d, s->p.N, s->p.L, s->p.R, eps, s->p.dt, s->p.bc, q);
     if (rc < 0) return rc;
+    q.scheme = s->p.scheme;
+    set_conditions(q);
+    rc = q.cond_ok ? ACE_OK : ACE_W_CONDITIONS;
     s->p = q;
     s->coef = coef_of(q);
     s->ck_count = 0;  // checkpoints of the old eps are no longer valid
     drop_graphs(s);   // captured launches carry the old coefficients
     return rc;
+}
+
+int ace_set_scheme(ace_solver *s, int scheme)
+{
+    if (!s || (scheme != ACE_SCHEME_RLB_MIE && scheme != ACE_SCHEME_FEX)) return ACE_E_ARG;
+    s->p.scheme = scheme;
+    set_conditions(s->p);
+    s->coef = coef_of(s->p);
+    s->ck_count = 0;
+    drop_graphs(s);
+    return s->p.cond_ok ? ACE_OK : ACE_W_CONDITIONS;
 }
 
 int ace_set_kernel(ace_solver *s, int kernel, int depth)
@@ -809,6 +836,7 @@ int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap)
 int ace_forward_ckpt(ace_solver *s, const double *phi0, int where, int64_t nsteps, int64_t every)
 {
     if (!s || !phi0 || nsteps < 0 || every < 1) return ACE_E_ARG;
+    if (s->p.scheme != ACE_SCHEME_RLB_MIE) return ACE_E_STATE;
     const int rc = ace_set_phi0(s, phi0, where);
     if (rc < 0) return rc;
     const int64_t total = s->p.total;

@@ -100,15 +100,28 @@ __device__ __forceinline__ double explicit_part(double p, double nsum, const Ste
     return fma(-c.h, f, t);
 }
 
+// The fully explicit comparison scheme of Sec. 3.3, Remark 2 (FEX-FD):
+// phi + kappa sum_k (phi_{+k} + phi_{-k} - 2 phi) - dt f(phi).
+template <int D>
+__device__ __forceinline__ double explicit_fex(double p, double nsum, const StepCoef &c)
+{
+    const double lap = fma(-2.0 * D, p, nsum);
+    const double t = fma(c.kappa, lap, p);
+    const double f = fma(p, p * p, -p);
+    return fma(-c.dt, f, t);
+}
+
 template <int D>
 __device__ __forceinline__ double update(double p, double nsum, const StepCoef &c)
 {
+    if (c.fex) return explicit_fex<D>(p, nsum, c);
     return cubic_root(explicit_part<D>(p, nsum, c), c);
 }
 
 template <int D, int NIT>
 __device__ __forceinline__ double update_n(double p, double nsum, const StepCoef &c)
 {
+    if (c.fex) return explicit_fex<D>(p, nsum, c);
     return cubic_root_n<NIT>(explicit_part<D>(p, nsum, c), c);
 }
 

@@ -17,6 +17,8 @@ struct StepCoef {
     double omh;
     double h3;
     int nit;
+    int fex;    // 1: the fully explicit comparison scheme (no cubic solve)
+    double dt;  // 2h, used by the explicit scheme
 };
 
 // Shape of one field: M[0] x M[1] x M[2] stored nodes in C order (unused

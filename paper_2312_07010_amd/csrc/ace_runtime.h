@@ -15,6 +15,7 @@ struct Problem {
     double dx, dt, eps, kappa, h;
     int nit;
     int cond_ok;
+    int scheme;  // ACE_SCHEME_*
 };
 
 int hip_status(hipError_t e);
