@@ -187,6 +187,13 @@ int ace_energy(ace_solver *s, double *E);
  * is NaN.  Synchronous; *m is host memory. */
 int ace_maxnorm(ace_solver *s, double *m);
 
+/* Volume of the phase phi > 0, measured smoothly as dx^d sum_i (1 + phi_i)/2
+ * (an odd interface profile makes this the volume inside the zero level
+ * set); from it the equivalent radius of the shrinking circle / sphere of
+ * the mean-curvature examples (Sec. 4.2.2).  Deterministic reduction.
+ * Synchronous; *V is host memory. */
+int ace_phase_volume(ace_solver *s, double *V);
+
 /* Copies the current field (total doubles, C order) to out. */
 int ace_get_phi(ace_solver *s, double *out, int where);
 

@@ -402,3 +402,15 @@ void oracle_root_array(long n, const double *xi, double h, double *out)
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < n; ++i) out[i] = oracle_root(xi[i], h);
 }
+
+/* Volume of the phase phi > 0, measured smoothly as dx^d sum (1 + phi)/2
+ * (the tanh profile across the interface is odd, so this equals the volume
+ * enclosed by the zero level set up to curvature corrections).  Used for the
+ * equivalent radius in the mean-curvature examples of Sec. 4.2.2.         */
+double oracle_phase_volume(int d, const long *M, double dx, const double *phi)
+{
+    const long n = oracle_total(d, M);
+    neumaier_t acc = {0, 0};
+    for (long i = 0; i < n; ++i) nsum_add(&acc, 0.5 * (1.0 + phi[i]));
+    return pow(dx, d) * nsum_get(&acc);
+}

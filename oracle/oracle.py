@@ -5,6 +5,7 @@ Only the test suite, the smoke check and the benchmark's CPU-baseline leg
 may import this module.  Nothing here is shared with the GPU library.
 """
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -57,6 +58,8 @@ def lib():
         L.oracle_run_scheme.argtypes = [ctypes.c_int, _L, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_double, _D, ctypes.c_long, ctypes.c_long, _D, _D, ctypes.c_int]
         L.oracle_run_scheme.restype = ctypes.c_int
+        L.oracle_phase_volume.argtypes = [ctypes.c_int, _L, ctypes.c_double, _D]
+        L.oracle_phase_volume.restype = ctypes.c_double
         L.oracle_adjoint.argtypes = [ctypes.c_int, _L, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                      _D, ctypes.c_long, _D, _D, _D]
         L.oracle_adjoint.restype = ctypes.c_int
@@ -150,6 +153,17 @@ class Problem:
     def grad_sum(self, phi):
         phi = _f64(phi).reshape(self.shape)
         return lib().oracle_grad_sum(self.d, self._Marr, self.bc, _dp(phi))
+
+    def phase_volume(self, phi):
+        phi = _f64(phi).reshape(self.shape)
+        return lib().oracle_phase_volume(self.d, self._Marr, self.dx, _dp(phi))
+
+    def equivalent_radius(self, phi):
+        """Radius of the disc (d = 2) or ball (d = 3) with the phase volume."""
+        V = self.phase_volume(phi)
+        if self.d == 2:
+            return math.sqrt(V / math.pi)
+        return (3 * V / (4 * math.pi)) ** (1.0 / 3.0)
 
     def maxnorm(self, phi):
         phi = _f64(phi)

@@ -79,6 +79,7 @@ _SIGS = {
     "ace_energy": (ctypes.c_int, [_vp, _P(_dbl)]),
     "ace_maxnorm": (ctypes.c_int, [_vp, _P(_dbl)]),
     "ace_get_phi": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "ace_phase_volume": (ctypes.c_int, [_vp, _P(_dbl)]),
     "ace_step_count": (_i64, [_vp]),
     "ace_field_ptr": (_vp, [_vp]),
     "ace_adjoint": (ctypes.c_int, [_vp, _vp, _i64, _i64, _vp, _vp, _P(_dbl), ctypes.c_int]),
@@ -261,6 +262,16 @@ class Solver:
         v = _dbl()
         _check(lib().ace_maxnorm(self._h, ctypes.byref(v)), "ace_maxnorm")
         return v.value
+
+    def phase_volume(self):
+        v = _dbl()
+        _check(lib().ace_phase_volume(self._h, ctypes.byref(v)), "ace_phase_volume")
+        return v.value
+
+    def equivalent_radius(self):
+        """Radius of the disc (d = 2) or ball (d = 3) holding the phase volume."""
+        V = self.phase_volume()
+        return (V / np.pi) ** 0.5 if self.d == 2 else (3 * V / (4 * np.pi)) ** (1.0 / 3.0)
 
     def get_phi(self, out=None):
         if out is not None and _is_device(out):

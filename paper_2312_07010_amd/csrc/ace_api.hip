@@ -727,6 +727,18 @@ int ace_maxnorm(ace_solver *s, double *m)
     return isfinite(*m) ? ACE_OK : ACE_E_NONFINITE;
 }
 
+int ace_phase_volume(ace_solver *s, double *V)
+{
+    if (!s || !V) return ACE_E_ARG;
+    ACE_TRY(grow(&s->partials, &s->partials_cap, phase_partials_needed()));
+    ACE_TRY(grow(&s->mon, &s->mon_cap, 3));
+    ACE_HIP(launch_phase_volume(s->buf[s->cur], s->p.total, s->partials, s->mon, s->stream));
+    double t[3];
+    ACE_TRY(read_triple(s, s->mon, t));
+    *V = pow(s->p.dx, s->p.d) * t[0];
+    return isfinite(*V) ? ACE_OK : ACE_E_NONFINITE;
+}
+
 int ace_get_phi(ace_solver *s, double *out, int where)
 {
     if (!s || !out || (where != ACE_HOST && where != ACE_DEVICE)) return ACE_E_ARG;

@@ -81,6 +81,11 @@ hipError_t launch_adjoint_step(const Shape &s, const StepCoef &c, const double *
                                double *lam_out, double *gpart, int64_t *nparts,
                                hipStream_t st);
 int64_t adjoint_partials_needed(const Shape &s);
+// out[0] = sum_i (1 + f_i)/2 over n values (fixed order, two passes through
+// part, which holds phase_partials_needed() doubles).
+int64_t phase_partials_needed();
+hipError_t launch_phase_volume(const double *f, int64_t n, double *part, double *out,
+                               hipStream_t st);
 // Fixed-order sum of n doubles into out[0] (+= if accumulate).
 hipError_t launch_sum(const double *x, int64_t n, double *out, int accumulate,
                       hipStream_t st);

@@ -239,6 +239,24 @@ __global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ part
     block_reduce_store(m, lds, out);
 }
 
+// Per-block partial sums of (1 + phi)/2 (the smooth phase indicator), each
+// block over a contiguous range in a fixed order.
+constexpr int kPhaseBlocks = 1024;
+__global__ __launch_bounds__(256) void k_phase_partials(const double *__restrict__ f, int64_t n,
+                                                        double *__restrict__ part)
+{
+    __shared__ double lds[4];
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * per;
+    const int64_t hi = (lo + per < n) ? lo + per : n;
+    double v = 0.0;
+    for (int64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) v += 0.5 * (1.0 + f[j]);
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = ((lds[0] + lds[1]) + (lds[2] + lds[3]));
+}
+
 __global__ __launch_bounds__(1024) void k_sum(const double *__restrict__ x, int64_t n,
                                               double *__restrict__ out, int accumulate)
 {
@@ -296,6 +314,17 @@ hipError_t launch_monitor(const Shape &s, const double *in, double *partials, in
 hipError_t launch_reduce(const double *partials, int64_t nparts, double *out, hipStream_t st)
 {
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partials, nparts, out);
+    return hipGetLastError();
+}
+
+int64_t phase_partials_needed() { return kPhaseBlocks; }
+
+hipError_t launch_phase_volume(const double *f, int64_t n, double *part, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_phase_partials, dim3(kPhaseBlocks), dim3(256), 0, st, f, n, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(1024), 0, st, part, (int64_t)kPhaseBlocks, out, 0);
     return hipGetLastError();
 }
 
