@@ -220,15 +220,18 @@ struct ace_solver {
     int64_t steps = 0;
     int kernel = ACE_KERNEL_AUTO;
     int depth = 0;
-    int zchunk = 32;  // planes per workgroup of the temporal-blocking kernel
+    int zchunk = 32;  // planes per workgroup of the 3D temporal-blocking kernel
+    int depth2 = 4;   // steps per launch of the 2D temporal-blocking kernel
     int tuned_kernel = 0;  // autotuned choice for ACE_KERNEL_AUTO (0: none)
     // reverse mode
     double *ckpt = nullptr;
     int64_t ckpt_cap = 0;
     int64_t ck_every = 0, ck_steps = 0, ck_count = 0;
     int64_t ck_field_version = -1;
-    double *seg = nullptr;
+    double *seg = nullptr;  // two segment buffers, (every + 1) states each
     int64_t seg_cap = 0;
+    hipStream_t aux = nullptr;  // recompute stream of the pipelined reverse sweep
+    hipEvent_t ev_start = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
     double *lam = nullptr;
     int64_t lam_cap = 0;
     double *gpart = nullptr;
@@ -239,7 +242,7 @@ struct ace_solver {
     int64_t graph_launches = 32;
     hipStream_t capture = nullptr;
     struct GraphEntry {
-        int kernel, zchunk, cur;
+        int kernel, zchunk, depth2, cur;
         const double *b0, *b1;
         hipGraph_t g;
         hipGraphExec_t e;
@@ -249,25 +252,37 @@ struct ace_solver {
 
 namespace {
 
+bool tblock_applies(const ace_solver *s)
+{
+    return (s->p.d == 3 && tblock_supported(s->shape)) || (s->p.d == 2 && tblock2d_supported(s->shape));
+}
+
 int effective_kernel(const ace_solver *s)
 {
     int k = s->kernel;
     if (k == ACE_KERNEL_AUTO) k = s->tuned_kernel;
     if (k == ACE_KERNEL_AUTO) {
         if (s->p.total <= RESIDENT_MAX) k = ACE_KERNEL_RESIDENT;
-        else if (s->p.d == 3) k = ACE_KERNEL_TBLOCK;
+        else if (s->p.d >= 2) k = ACE_KERNEL_TBLOCK;
         else k = ACE_KERNEL_DIRECT;
     }
     if (k == ACE_KERNEL_RESIDENT && s->p.total > RESIDENT_MAX) k = ACE_KERNEL_DIRECT;
-    if (k == ACE_KERNEL_TBLOCK && !tblock_supported(s->shape)) k = ACE_KERNEL_DIRECT;
+    if (k == ACE_KERNEL_TBLOCK && !tblock_applies(s)) k = ACE_KERNEL_DIRECT;
     if (k == ACE_KERNEL_MARCH && !march_supported(s->shape)) k = ACE_KERNEL_DIRECT;
     return k;
 }
 
-// One launch from buf[cur] into buf[cur^1] advancing 1 step (or 2 with the
-// temporal-blocking kernel when at least 2 remain).  If want_mon, the monitor
-// partials of the input field are left in s->partials, their count in
-// *nparts.  Returns the number of steps taken (or a negative error).
+// Steps one launch of `kernel` advances (in a long enough run).
+int steps_per_launch_of(const ace_solver *s, int kernel)
+{
+    if (kernel != ACE_KERNEL_TBLOCK) return 1;
+    return (s->p.d == 3) ? 2 : s->depth2;
+}
+
+// One launch from buf[cur] into buf[cur^1] advancing 1 step, or up to
+// steps_per_launch_of() with the temporal-blocking kernels.  If want_mon,
+// the monitor partials of the input field are left in s->partials, their
+// count in *nparts.  Returns the number of steps taken (or a negative error).
 int launch_steps(ace_solver *s, int kernel, int64_t remaining, bool want_mon, int64_t *nparts)
 {
     const double *in = s->buf[s->cur];
@@ -275,7 +290,10 @@ int launch_steps(ace_solver *s, int kernel, int64_t remaining, bool want_mon, in
     double *parts = want_mon ? s->partials : nullptr;
     hipError_t e;
     int taken = 1;
-    if (kernel == ACE_KERNEL_TBLOCK && remaining >= 2) {
+    if (kernel == ACE_KERNEL_TBLOCK && s->p.d == 2) {
+        taken = (int)std::min<int64_t>(s->depth2, remaining);
+        e = launch_step_tblock2d(s->shape, s->coef, in, out, parts, nparts, taken, 0, s->stream);
+    } else if (kernel == ACE_KERNEL_TBLOCK && remaining >= 2) {
         e = launch_step_tblock2(s->shape, s->coef, in, out, parts, nparts, s->zchunk, s->stream);
         taken = 2;
     } else if (kernel == ACE_KERNEL_MARCH || kernel == ACE_KERNEL_TBLOCK) {
@@ -304,8 +322,8 @@ void drop_graphs(ace_solver *s)
 int graph_for(ace_solver *s, int kernel, hipGraphExec_t *out)
 {
     for (auto &g : s->graphs)
-        if (g.kernel == kernel && g.zchunk == s->zchunk && g.cur == s->cur && g.b0 == s->buf[0] &&
-            g.b1 == s->buf[1]) {
+        if (g.kernel == kernel && g.zchunk == s->zchunk && g.depth2 == s->depth2 && g.cur == s->cur &&
+            g.b0 == s->buf[0] && g.b1 == s->buf[1]) {
             *out = g.e;
             return ACE_OK;
         }
@@ -316,8 +334,9 @@ int graph_for(ace_solver *s, int kernel, hipGraphExec_t *out)
     s->stream = s->capture;
     ACE_HIP(hipStreamBeginCapture(s->capture, hipStreamCaptureModeThreadLocal));
     int rc = ACE_OK;
+    const int per = steps_per_launch_of(s, kernel);
     for (int64_t i = 0; i < s->graph_launches && rc >= 0; ++i) {
-        const int t = launch_steps(s, kernel, kernel == ACE_KERNEL_TBLOCK ? 2 : 1, false, nullptr);
+        const int t = launch_steps(s, kernel, per, false, nullptr);
         if (t < 0) rc = t;
     }
     hipGraph_t g = nullptr;
@@ -336,7 +355,7 @@ int graph_for(ace_solver *s, int kernel, hipGraphExec_t *out)
         (void)hipGraphDestroy(g);
         return hip_status(ie);
     }
-    s->graphs.push_back({kernel, s->zchunk, cur0, s->buf[0], s->buf[1], g, e});
+    s->graphs.push_back({kernel, s->zchunk, s->depth2, cur0, s->buf[0], s->buf[1], g, e});
     *out = e;
     return ACE_OK;
 }
@@ -350,7 +369,7 @@ int advance(ace_solver *s, int64_t nsteps)
         s->steps += nsteps;
         return ACE_OK;
     }
-    const int per = (k == ACE_KERNEL_TBLOCK) ? 2 : 1;
+    const int per = steps_per_launch_of(s, k);
     int64_t i = 0;
     if (s->graph_launches >= 2) {
         const int64_t chunk = s->graph_launches * per;
@@ -383,6 +402,8 @@ int alloc_fields(ace_solver *s)
     if (march_supported(s->shape)) need2 = std::max<int64_t>(need2, 3 * march_partials_needed(s->shape));
     if (tblock_supported(s->shape))
         need2 = std::max<int64_t>(need2, 3 * tblock_partials_needed(s->shape, TBLOCK_MIN_ZCHUNK));
+    if (tblock2d_supported(s->shape))
+        need2 = std::max<int64_t>(need2, 3 * tblock2d_blocks(s->shape, tblock2d_max_depth()));
     ACE_TRY(grow(&s->partials, &s->partials_cap, need2));
     ACE_HIP(hipHostMalloc((void **)&s->pinned, 64 * sizeof(double), hipHostMallocDefault));
     return ACE_OK;
@@ -406,7 +427,7 @@ int monitor_now(ace_solver *s, double *dev_out)
 }
 
 // Autotuner cache: one line per tuned problem shape,
-//   ace-tune <d> <bc> <M0> <M1> <M2> <kernel> <zchunk> <ms_per_step>
+//   ace-tune <d> <bc> <M0> <M1> <M2> <kernel> <zchunk> <depth2> <ms_per_step>
 // appended by ace_autotune; the last matching line wins.
 void load_tuning(ace_solver *s)
 {
@@ -416,16 +437,18 @@ void load_tuning(ace_solver *s)
     if (!f) return;
     char line[256];
     while (fgets(line, sizeof line, f)) {
-        int d, bc, k, zc;
+        int d, bc, k, zc, k2;
         long long m0, m1, m2;
         double ms;
-        if (sscanf(line, "ace-tune %d %d %lld %lld %lld %d %d %lf", &d, &bc, &m0, &m1, &m2, &k, &zc,
-                   &ms) != 8)
+        if (sscanf(line, "ace-tune %d %d %lld %lld %lld %d %d %d %lf", &d, &bc, &m0, &m1, &m2, &k,
+                   &zc, &k2, &ms) != 9)
             continue;
         if (d == s->p.d && bc == s->p.bc && m0 == s->p.M[0] && m1 == s->p.M[1] && m2 == s->p.M[2] &&
-            k >= ACE_KERNEL_DIRECT && k <= ACE_KERNEL_TBLOCK && zc >= TBLOCK_MIN_ZCHUNK) {
+            k >= ACE_KERNEL_DIRECT && k <= ACE_KERNEL_TBLOCK && zc >= TBLOCK_MIN_ZCHUNK && k2 >= 1 &&
+            k2 <= tblock2d_max_depth()) {
             s->tuned_kernel = k;
             s->zchunk = zc;
+            s->depth2 = k2;
         }
     }
     fclose(f);
@@ -491,6 +514,10 @@ int ace_destroy(ace_solver *s)
     if (!s) return ACE_E_ARG;
     drop_graphs(s);
     if (s->capture) (void)hipStreamDestroy(s->capture);
+    if (s->aux) (void)hipStreamDestroy(s->aux);
+    hipEvent_t evs[] = {s->ev_start, s->ev_rec[0], s->ev_rec[1], s->ev_rev[0], s->ev_rev[1]};
+    for (hipEvent_t e : evs)
+        if (e) (void)hipEventDestroy(e);
     for (int i = 0; i < 2; ++i)
         if (s->own[i]) (void)hipFree(s->own[i]);
     double *devs[] = {s->partials, s->mon, s->ckpt, s->seg, s->lam, s->gpart, s->gsum};
@@ -613,7 +640,11 @@ int ace_set_scheme(ace_solver *s, int scheme)
 int ace_set_kernel(ace_solver *s, int kernel, int depth)
 {
     if (!s || kernel < ACE_KERNEL_AUTO || kernel > ACE_KERNEL_TBLOCK || depth < 0) return ACE_E_ARG;
-    if (kernel == ACE_KERNEL_TBLOCK && depth != 0 && depth != 2) return ACE_E_ARG;
+    if (kernel == ACE_KERNEL_TBLOCK && depth != 0) {
+        if (s->p.d == 3 && depth != 2) return ACE_E_ARG;
+        if (s->p.d == 2 && depth > tblock2d_max_depth()) return ACE_E_ARG;
+        if (s->p.d == 2) s->depth2 = depth;
+    }
     s->kernel = kernel;
     s->depth = depth;
     return ACE_OK;
@@ -624,7 +655,7 @@ int ace_get_kernel(const ace_solver *s, int *kernel, int *steps_per_launch)
     if (!s || !kernel) return ACE_E_ARG;
     const int k = effective_kernel(s);
     *kernel = k;
-    if (steps_per_launch) *steps_per_launch = (k == ACE_KERNEL_TBLOCK) ? 2 : 1;
+    if (steps_per_launch) *steps_per_launch = steps_per_launch_of(s, k);
     return ACE_OK;
 }
 
@@ -758,21 +789,24 @@ int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap)
 {
     if (!s || trial_steps < 1) return ACE_E_ARG;
     struct Cand {
-        int kernel, zchunk;
+        int kernel, zchunk, depth2;
     };
     std::vector<Cand> cands;
-    cands.push_back({ACE_KERNEL_DIRECT, s->zchunk});
-    if (s->p.total <= RESIDENT_MAX) cands.push_back({ACE_KERNEL_RESIDENT, s->zchunk});
-    if (march_supported(s->shape)) cands.push_back({ACE_KERNEL_MARCH, s->zchunk});
-    if (tblock_supported(s->shape))
+    cands.push_back({ACE_KERNEL_DIRECT, s->zchunk, s->depth2});
+    if (s->p.total <= RESIDENT_MAX) cands.push_back({ACE_KERNEL_RESIDENT, s->zchunk, s->depth2});
+    if (march_supported(s->shape)) cands.push_back({ACE_KERNEL_MARCH, s->zchunk, s->depth2});
+    if (s->p.d == 3 && tblock_supported(s->shape))
         for (int zc : {16, 24, 32, 40, 48, 64, 128})
-            if (zc <= std::max<int64_t>(s->shape.M0, 16)) cands.push_back({ACE_KERNEL_TBLOCK, zc});
+            if (zc <= std::max<int64_t>(s->shape.M0, 16)) cands.push_back({ACE_KERNEL_TBLOCK, zc, s->depth2});
+    if (s->p.d == 2 && tblock2d_supported(s->shape))
+        for (int k2 : {1, 2, 4, 6, 8, 12})
+            if (k2 <= tblock2d_max_depth()) cands.push_back({ACE_KERNEL_TBLOCK, s->zchunk, k2});
     const int64_t total = s->p.total;
     double *save = nullptr;
     ACE_HIP(hipMalloc((void **)&save, sizeof(double) * total));
     const int cur0 = s->cur;
     const int64_t steps0 = s->steps;
-    const int kernel0 = s->kernel, zchunk0 = s->zchunk;
+    const int kernel0 = s->kernel, zchunk0 = s->zchunk, depth20 = s->depth2;
     int rc = hip_status(hipMemcpyAsync(save, s->buf[cur0], sizeof(double) * total,
                                        hipMemcpyDeviceToDevice, s->stream));
     auto restore = [&]() {
@@ -792,6 +826,7 @@ int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap)
         if (rc < 0) break;
         s->kernel = c.kernel;
         s->zchunk = c.zchunk;
+        s->depth2 = c.depth2;
         if ((rc = restore()) < 0) break;
         if ((rc = advance(s, 2)) < 0) break;  // warm-up (loads the code object)
         if ((rc = restore()) < 0) break;
@@ -803,8 +838,9 @@ int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap)
         (void)hipEventElapsedTime(&ms, e0, e1);
         const double per = ms / (double)trial_steps;
         char buf[200];
-        snprintf(buf, sizeof buf, "%s{\"kernel\": %d, \"zchunk\": %d, \"ms_per_step\": %.6f}",
-                 first ? "" : ", ", c.kernel, c.zchunk, per);
+        snprintf(buf, sizeof buf,
+                 "%s{\"kernel\": %d, \"zchunk\": %d, \"depth2\": %d, \"ms_per_step\": %.6f}",
+                 first ? "" : ", ", c.kernel, c.zchunk, c.depth2, per);
         rec += buf;
         first = false;
         if (per < best_ms) {
@@ -816,6 +852,7 @@ int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap)
     if (e1) (void)hipEventDestroy(e1);
     s->kernel = kernel0;
     s->zchunk = zchunk0;
+    s->depth2 = depth20;
     if (rc >= 0) rc = restore();
     if (rc >= 0) rc = hip_status(hipStreamSynchronize(s->stream));
     (void)hipFree(save);
@@ -823,18 +860,21 @@ int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap)
     if (rc < 0) return rc;
     s->tuned_kernel = best.kernel;
     s->zchunk = best.zchunk;
+    s->depth2 = best.depth2;
+    drop_graphs(s);
     char buf[200];
-    snprintf(buf, sizeof buf, "], \"choice\": {\"kernel\": %d, \"zchunk\": %d, \"ms_per_step\": %.6f}}",
-             best.kernel, best.zchunk, best_ms);
+    snprintf(buf, sizeof buf,
+             "], \"choice\": {\"kernel\": %d, \"zchunk\": %d, \"depth2\": %d, \"ms_per_step\": %.6f}}",
+             best.kernel, best.zchunk, best.depth2, best_ms);
     rec += buf;
     if (json && cap > 0) snprintf(json, cap, "%s", rec.c_str());
     const char *path = getenv("ACE_AUTOTUNE_CACHE");
     if (path) {
         FILE *f = fopen(path, "a");
         if (f) {
-            fprintf(f, "ace-tune %d %d %lld %lld %lld %d %d %.6f\n", s->p.d, s->p.bc,
+            fprintf(f, "ace-tune %d %d %lld %lld %lld %d %d %d %.6f\n", s->p.d, s->p.bc,
                     (long long)s->p.M[0], (long long)s->p.M[1], (long long)s->p.M[2], best.kernel,
-                    best.zchunk, best_ms);
+                    best.zchunk, best.depth2, best_ms);
             fclose(f);
         }
     }
@@ -855,9 +895,12 @@ int ace_forward_ckpt(ace_solver *s, const double *phi0, int where, int64_t nstep
     const int64_t nck = nsteps == 0 ? 1 : (nsteps + every - 1) / every;
     ACE_TRY(grow(&s->ckpt, &s->ckpt_cap, nck * total));
     // size the reverse sweep's buffers now so ace_backward allocates nothing
-    ACE_TRY(grow(&s->seg, &s->seg_cap, (every + 1) * total));
+    ACE_TRY(grow(&s->seg, &s->seg_cap, 2 * (every + 1) * total));
     ACE_TRY(grow(&s->lam, &s->lam_cap, 2 * total));
-    ACE_TRY(grow(&s->gpart, &s->gpart_cap, adjoint_partials_needed(s->shape) * every));
+    int64_t per_step = adjoint_partials_needed(s->shape);
+    if (tblock2d_supported(s->shape))
+        per_step = std::max<int64_t>(per_step, tblock2d_blocks(s->shape, tblock2d_max_depth()));
+    ACE_TRY(grow(&s->gpart, &s->gpart_cap, per_step * every));
     const size_t bytes = (size_t)total * sizeof(double);
     for (int64_t j = 0; j < nck; ++j) {
         ACE_HIP(hipMemcpyAsync(s->ckpt + j * total, s->buf[s->cur], bytes, hipMemcpyDeviceToDevice,
@@ -880,40 +923,83 @@ int ace_backward(ace_solver *s, const double *lambdaT, double *dphi0, double *de
     if (s->ck_count <= 0 || s->ck_field_version != s->field_version) return ACE_E_STATE;
     const int64_t total = s->p.total, every = s->ck_every, nsteps = s->ck_steps;
     const size_t bytes = (size_t)total * sizeof(double);
-    ACE_TRY(grow(&s->seg, &s->seg_cap, (every + 1) * total));
-    ACE_TRY(grow(&s->lam, &s->lam_cap, 2 * total));
+    if (s->seg_cap < 2 * (every + 1) * total || s->lam_cap < 2 * total) return ACE_E_STATE;
     const int64_t npart = adjoint_partials_needed(s->shape);
-    ACE_TRY(grow(&s->gpart, &s->gpart_cap, npart * every));
     double *lam[2] = {s->lam, s->lam + total};
     int lc = 0;
+    // The reverse sweep of segment j (on the handle's stream) and the
+    // recompute of segment j-1 (on a second stream) are independent, so they
+    // run concurrently on alternating segment buffers; events order each
+    // buffer's recompute after the previous sweep that used it, and each sweep
+    // after its recompute.
+    if (!s->aux) ACE_HIP(hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking));
+    if (!s->ev_start) {
+        ACE_HIP(hipEventCreateWithFlags(&s->ev_start, hipEventDisableTiming));
+        for (int b = 0; b < 2; ++b) {
+            ACE_HIP(hipEventCreateWithFlags(&s->ev_rec[b], hipEventDisableTiming));
+            ACE_HIP(hipEventCreateWithFlags(&s->ev_rev[b], hipEventDisableTiming));
+        }
+    }
     ACE_HIP(hipMemcpyAsync(lam[0], lambdaT, bytes,
                            where == ACE_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
                            s->stream));
     ACE_HIP(hipMemsetAsync(s->gsum, 0, sizeof(double), s->stream));
-    // recompute segments with the single-step kernels so each state lands in
-    // its own slot of the segment buffer
+    ACE_HIP(hipEventRecord(s->ev_start, s->stream));  // checkpoints are complete
+    ACE_HIP(hipStreamWaitEvent(s->aux, s->ev_start, 0));
     int k = effective_kernel(s);
     if (k == ACE_KERNEL_RESIDENT) k = ACE_KERNEL_DIRECT;
-    if (k == ACE_KERNEL_TBLOCK) k = ACE_KERNEL_MARCH;
+    const bool blocked2d = (k == ACE_KERNEL_TBLOCK && s->p.d == 2);
+    if (k == ACE_KERNEL_TBLOCK && !blocked2d) k = ACE_KERNEL_MARCH;
     for (int64_t j = s->ck_count - 1; j >= 0; --j) {
+        const int b = (int)(j & 1);
+        double *seg = s->seg + b * (every + 1) * total;
         const int64_t a = j * every;
         const int64_t n = std::min<int64_t>(every, nsteps - a);
-        ACE_HIP(hipMemcpyAsync(s->seg, s->ckpt + j * total, bytes, hipMemcpyDeviceToDevice, s->stream));
-        for (int64_t i = 0; i < n; ++i) {
-            const double *in = s->seg + i * total;
-            double *out = s->seg + (i + 1) * total;
-            hipError_t e = (k == ACE_KERNEL_MARCH)
-                               ? launch_step_march(s->shape, s->coef, in, out, nullptr, nullptr, s->stream)
-                               : launch_step_direct(s->shape, s->coef, in, out, nullptr, nullptr, s->stream);
-            ACE_HIP(e);
+        // --- recompute segment j on the second stream ---
+        ACE_HIP(hipStreamWaitEvent(s->aux, s->ev_rev[b], 0));
+        ACE_HIP(hipMemcpyAsync(seg, s->ckpt + j * total, bytes, hipMemcpyDeviceToDevice, s->aux));
+        if (blocked2d) {
+            for (int64_t i = 0; i < n;) {  // each launch writes its K intermediate states
+                const int K = (int)std::min<int64_t>(s->depth2, n - i);
+                ACE_HIP(launch_step_tblock2d(s->shape, s->coef, seg + i * total, seg + (i + 1) * total,
+                                             nullptr, nullptr, K, total, s->aux));
+                i += K;
+            }
+        } else {
+            for (int64_t i = 0; i < n; ++i) {
+                const double *in = seg + i * total;
+                double *out = seg + (i + 1) * total;
+                hipError_t e = (k == ACE_KERNEL_MARCH)
+                                   ? launch_step_march(s->shape, s->coef, in, out, nullptr, nullptr, s->aux)
+                                   : launch_step_direct(s->shape, s->coef, in, out, nullptr, nullptr, s->aux);
+                ACE_HIP(e);
+            }
         }
-        for (int64_t i = n - 1; i >= 0; --i) {
-            ACE_HIP(launch_adjoint_step(s->shape, s->coef, lam[lc], s->seg + i * total,
-                                        s->seg + (i + 1) * total, lam[lc ^ 1],
-                                        s->gpart + i * npart, nullptr, s->stream));
-            lc ^= 1;
+        ACE_HIP(hipEventRecord(s->ev_rec[b], s->aux));
+        // --- reverse sweep of segment j on the handle's stream ---
+        ACE_HIP(hipStreamWaitEvent(s->stream, s->ev_rec[b], 0));
+        int64_t parts = 0;  // partial sums of dL/dkappa written for this segment
+        if (blocked2d) {
+            const int64_t nb = tblock2d_blocks(s->shape, s->depth2);
+            for (int64_t i = n; i > 0;) {  // K transposed steps per launch
+                const int K = (int)std::min<int64_t>(s->depth2, i);
+                ACE_HIP(launch_adjoint_tblock2d(s->shape, s->coef, lam[lc], seg + (i - K) * total, total,
+                                                lam[lc ^ 1], s->gpart + parts, K, s->stream));
+                parts += (K == s->depth2) ? nb : tblock2d_blocks(s->shape, K);
+                lc ^= 1;
+                i -= K;
+            }
+        } else {
+            for (int64_t i = n - 1; i >= 0; --i) {
+                ACE_HIP(launch_adjoint_step(s->shape, s->coef, lam[lc], seg + i * total,
+                                            seg + (i + 1) * total, lam[lc ^ 1], s->gpart + parts,
+                                            nullptr, s->stream));
+                parts += npart;
+                lc ^= 1;
+            }
         }
-        if (n > 0) ACE_HIP(launch_sum(s->gpart, n * npart, s->gsum, 1, s->stream));
+        if (parts > 0) ACE_HIP(launch_sum(s->gpart, parts, s->gsum, 1, s->stream));
+        ACE_HIP(hipEventRecord(s->ev_rev[b], s->stream));
     }
     ACE_HIP(hipMemcpyAsync(dphi0, lam[lc], bytes,
                            where == ACE_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,

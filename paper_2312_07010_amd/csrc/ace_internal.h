@@ -73,6 +73,22 @@ bool tblock_supported(const Shape &s);
 int64_t tblock_partials_needed(const Shape &s, int zchunk);
 constexpr int TBLOCK_MIN_ZCHUNK = 8;
 
+// 2D: K steps per launch on LDS regions (1 <= K <= tblock2d_max_depth()).
+// With level_stride > 0 every intermediate level k = 1..K is written to
+// out + (k-1) * level_stride (the adjoint's segment recompute); otherwise only
+// level K goes to out.  Same partials contract as the one-step kernels.
+hipError_t launch_step_tblock2d(const Shape &s, const StepCoef &c, const double *in,
+                                double *out, double *partials, int64_t *nparts, int K,
+                                int64_t level_stride, hipStream_t st);
+// K transposed steps: states[i * stride] = phi^{m+i}, i = 0..K; lam_in =
+// lambda^{m+K}; writes lambda^m and one partial of dL/dkappa per block.
+hipError_t launch_adjoint_tblock2d(const Shape &s, const StepCoef &c, const double *lam_in,
+                                   const double *states, int64_t stride, double *lam_out,
+                                   double *gpart, int K, hipStream_t st);
+bool tblock2d_supported(const Shape &s);
+int tblock2d_max_depth();
+int64_t tblock2d_blocks(const Shape &s, int K);
+
 // Adjoint step (reverse sweep) for one step n: reads lam (lambda^{n+1}),
 // phin (phi^n), phin1 (phi^{n+1}); writes lam_out (lambda^n) and per-block
 // partial sums of <mu, Lambda phi^n> into gpart (count in *nparts).

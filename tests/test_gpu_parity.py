@@ -53,12 +53,15 @@ def test_one_and_many_steps_all_kernels(ace, orc, d, bc, N):
     phi0 = rng.uniform(-1, 1, p.shape)
     want1 = p.step(phi0)
     want30, _, _ = p.run(phi0, 30)
-    kernels = [ace.ACE_KERNEL_DIRECT, ace.ACE_KERNEL_RESIDENT]
+    kernels = [(ace.ACE_KERNEL_DIRECT, 0), (ace.ACE_KERNEL_RESIDENT, 0)]
     if d == 3:
-        kernels += [ace.ACE_KERNEL_MARCH, ace.ACE_KERNEL_TBLOCK]
+        kernels += [(ace.ACE_KERNEL_MARCH, 0), (ace.ACE_KERNEL_TBLOCK, 0)]
+    if d == 2:
+        kernels += [(ace.ACE_KERNEL_TBLOCK, 1), (ace.ACE_KERNEL_TBLOCK, 3), (ace.ACE_KERNEL_TBLOCK, 8),
+                    (ace.ACE_KERNEL_TBLOCK, 12)]
     outs = []
-    for k in kernels:
-        s.set_kernel(k)
+    for k, depth in kernels:
+        s.set_kernel(k, depth)
         s.set_phi0(phi0)
         s.step(1)
         got1 = s.get_phi()
@@ -79,7 +82,7 @@ def test_monitored_run_matches_oracle(ace, orc, d, bc, N):
     phi0 = rng.uniform(-0.9, 0.9, p.shape)
     want, Ew, mw = p.run(phi0, 50, 10)
     kernels = [ace.ACE_KERNEL_DIRECT, ace.ACE_KERNEL_RESIDENT]
-    kernels += [ace.ACE_KERNEL_MARCH, ace.ACE_KERNEL_TBLOCK] if d == 3 else []
+    kernels += [ace.ACE_KERNEL_MARCH, ace.ACE_KERNEL_TBLOCK] if d >= 2 else []
     for k in kernels:
         s.set_kernel(k)
         s.set_phi0(phi0)
@@ -195,3 +198,33 @@ def test_3d_ragged_box_all_kernels(ace, orc, bc):
         np.testing.assert_allclose(m, mw, rtol=0, atol=1e-13)
         outs.append(got)
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+@pytest.mark.parametrize("bc", [0, 1, 2])
+@pytest.mark.parametrize("shape", [(3, 5), (40, 61), (100, 257), (7, 300)])
+def test_2d_blocked_ragged_rectangles(ace, orc, bc, shape):
+    """2D temporal blocking on rectangles (equal spacing, different extents)
+    whose sides are not multiples of the tile, from tiny (the ring wraps the
+    periodic grid several times) to several tiles; every depth equals the
+    one-step kernel bit for bit and the oracle to 1e-13."""
+    N = [n + {0: -2, 1: 1, 2: 0}[bc] for n in shape]
+    N = [max(n, {0: 1, 1: 2, 2: 3}[bc]) for n in N]
+    dx = 1.0 / 64
+    R = [n * dx for n in N]
+    dt = 2e-3
+    eps = math.sqrt(0.2 * dx * dx / dt)
+    s = ace.Solver(2, N, [0.0, 0.0], R, eps, dt, bc)
+    p = orc.Problem(2, N, [0.0, 0.0], R, eps, dt, bc)
+    phi0 = np.random.default_rng(sum(shape) + bc).uniform(-1, 1, p.shape)
+    want, Ew, _ = p.run(phi0, 25, 5)
+    s.set_kernel(ace.ACE_KERNEL_DIRECT)
+    s.set_phi0(phi0)
+    s.step(25)
+    ref = s.get_phi()
+    np.testing.assert_allclose(ref, want, rtol=0, atol=1e-13)
+    for depth in (1, 2, 5, 12):
+        s.set_kernel(ace.ACE_KERNEL_TBLOCK, depth)
+        s.set_phi0(phi0)
+        E, _ = s.run_monitored(25, 5)
+        assert np.array_equal(s.get_phi(), ref), depth
+        np.testing.assert_allclose(E, Ew, rtol=1e-12)
