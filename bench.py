@@ -1,15 +1,16 @@
 """Throughput benchmark of the RLB-MIE-FD Allen-Cahn step on one MI355X.
 
-Workload: 3D periodic, 512^3 nodes on (0,1)^3, eps = 0.02, dt = 5e-4
-(kappa = 0.0524288), a tanh sphere of radius 0.3 plus Uniform[-0.01, 0.01]
-noise clipped to [-1, 1], energy and max-norm fused every 100 steps.  One
-bench step is one time step of the scheme over the whole field; the field is
-resident in HBM before timing starts.
+Workload (default): 3D periodic, 512^3 nodes on (0,1)^3, eps = 0.02,
+dt = 5e-4 (kappa = 0.0524288), a tanh sphere of radius 0.3 plus
+Uniform[-0.01, 0.01] noise clipped to [-1, 1], energy and max-norm fused
+every 100 steps.  One bench step is one time step of the scheme over the
+whole field; the field is resident in HBM before timing starts.  --workload
+2d / 1d time the 2D Neumann 1024^2 or the 1D periodic 256 workload instead.
 
 Prints one JSON line: updates/s, the HBM roofline of the step kernel (16
 algorithmic bytes per node update: read phi^n, write phi^{n+1}), the CPU
-oracle timed on a bounded sample, and the adjoint cost ratio / batched
-speed-up of the other two workloads.
+oracle timed on a bounded sample, the explicit comparison scheme, the other
+two single-field workloads, and the adjoint cost ratio / batched speed-up.
 """
 import argparse
 import hashlib
@@ -26,7 +27,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK = 8.0e12            # MI355X HBM3E, bytes/s
 BYTES_PER_UPDATE = 16.0      # read phi^n + write phi^{n+1}
 CSRC = os.path.join(ROOT, "paper_2312_07010_amd", "csrc")
-KERNEL_SRC = {"k_march3d": "ace_march.hip", "k_tblock3d": "ace_tblock.hip"}
+KERNEL_SRC = {"k_march3d": "ace_march.hip", "k_tblock3d": "ace_tblock.hip",
+              "k_tblock2d": "ace_tblock2d.hip"}
 
 
 def _sha(path):
@@ -34,11 +36,11 @@ def _sha(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(kname):
+def measured_traffic(kname, plane_chunk):
     """HBM bytes per launch of the step kernel from the committed rocprofv3
     FETCH_SIZE/WRITE_SIZE runs (scaled by a copy of known size), if they were
-    taken on the current source of that kernel and of the device header; else
-    None."""
+    taken on the current source of that kernel and of the device header and
+    at the same launch shape (planes per workgroup); else None."""
     path = os.path.join(ROOT, "profiles", f"{kname}_p512_traffic.json")
     try:
         with open(path) as f:
@@ -48,22 +50,38 @@ def measured_traffic(kname):
         return None
     if t.get("kernel_src_sha") != src:
         return None
-    return t.get("bytes_per_launch")
+    shapes = t.get("by_plane_chunk", {})
+    key = str(plane_chunk) if kname == "k_tblock3d" else "any"
+    return shapes.get(key, {}).get("bytes_per_launch")
 
 
-def cpu_baseline(w, phi0_full, sample_steps):
+def cpu_baseline(w, phi0_full, min_seconds=10.0):
     """The oracle as it stands, on a bounded sample of the same workload: the
-    full 512^3 field for `sample_steps` steps, all host threads."""
+    full field for as many steps as fill about `min_seconds`, once on all
+    host threads and once on one thread."""
     import oracle
     p = oracle.Problem(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
-    t0 = time.perf_counter()
-    p.run(phi0_full, sample_steps)
-    t = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    upd = float(np.prod(p.shape)) * sample_steps
-    return {"value": upd / t, "unit": "grid-pt updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{'x'.join(map(str, p.shape))} field, {sample_steps} steps "
-                      f"({upd:.3g} updates, {t:.1f} s)"}
+    n = float(np.prod(p.shape))
+
+    def leg(threads):
+        prev = oracle.set_threads(threads)
+        used = oracle.set_threads(0)
+        phi, t, steps, k = phi0_full, 0.0, 0, 1
+        while t < min_seconds:
+            t0 = time.perf_counter()
+            phi, _, _ = p.run(phi, k)
+            t += time.perf_counter() - t0
+            steps += k
+            k = max(1, int((min_seconds - t) / (t / steps)))
+        oracle.set_threads(prev)
+        return {"value": n * steps / t, "unit": "grid-pt updates/s", "cores": used,
+                "kind": "oracle",
+                "sample": f"{'x'.join(map(str, p.shape))} field, {steps} step(s) "
+                          f"({n * steps:.3g} updates, {t:.1f} s)"}
+
+    out = leg(0)
+    out["one_thread"] = leg(1)
+    return out
 
 
 def adjoint_ratio(ace, torch):
@@ -144,19 +162,104 @@ def batched_speedup(ace, torch):
             "resident_limit": tune["choice"]["resident_limit"]}
 
 
+WORKLOAD_DESC = {
+    "3d": "3D Allen-Cahn RLB-MIE-FD step, periodic, 512^3 nodes on (0,1)^3, eps 0.02, dt 5e-4, "
+          "tanh sphere r 0.3 + U[-0.01,0.01] noise, energy + max-norm fused every 100 steps",
+    "2d": "2D Allen-Cahn RLB-MIE-FD step, homogeneous Neumann, 1024^2 stored nodes (N = 1022) on "
+          "(0,1)^2, eps 0.01, dt 1e-3, U[-0.9,0.9], energy + max-norm fused every 100 steps",
+    "1d": "1D Allen-Cahn RLB-MIE-FD step, periodic, 256 nodes on (-1,1), eps 0.02, dt 1e-3, "
+          "U[-0.05,0.05], energy + max-norm fused every 100 steps",
+}
+
+
+def kernel_name(ace, d, kernel):
+    if kernel == ace.ACE_KERNEL_TBLOCK:
+        return "k_tblock3d" if d == 3 else "k_tblock2d"
+    return {ace.ACE_KERNEL_MARCH: "k_march3d", ace.ACE_KERNEL_DIRECT: "k_step_direct",
+            ace.ACE_KERNEL_RESIDENT: "k_resident"}.get(kernel, str(kernel))
+
+
+def launches_in(steps, every, per_launch):
+    """Step-kernel launches of ace_run_monitored(steps, every): each monitor
+    interval starts a new launch."""
+    n, left = 0, steps
+    while left > 0:
+        k = min(every, left)
+        n += -(-k // per_launch)
+        left -= k
+    return n
+
+
+def timed_workload(ace, torch, w, kernel="auto", plane_chunk=-1, autotune=True, steps=None,
+                   warmup=100, every=100, keep=False):
+    """ace_run_monitored(steps, every) on the workload's field, resident in
+    HBM, after `warmup` untimed steps; timed by the host clock and by HIP
+    events on the solver's stream (torch's current stream)."""
+    from paper_2312_07010_amd import inputs
+    steps = w.steps if steps is None else steps
+    s = ace.Solver(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
+    s.use_torch_stream()
+    kid = {"auto": ace.ACE_KERNEL_AUTO, "march": ace.ACE_KERNEL_MARCH,
+           "tblock": ace.ACE_KERNEL_TBLOCK, "direct": ace.ACE_KERNEL_DIRECT}[kernel]
+    s.set_kernel(kid)
+    coords = [s.coords(a) for a in range(w.d)]
+    phi0 = inputs.initial_field(w, s.shape, coords)
+    phi0_dev = torch.tensor(phi0, device="cuda")
+    s.set_phi0(phi0_dev)
+    tuning = None
+    if plane_chunk >= 0:
+        s.set_plane_chunk(plane_chunk)
+    elif kernel == "auto" and autotune:
+        tuning = json.loads(s.autotune(20))
+    k, per_launch = s.get_kernel()
+    s.set_phi0(phi0_dev)
+    s.run_monitored(warmup, every)  # also loads every kernel variant used below
+    torch.cuda.synchronize()
+    s.set_phi0(phi0_dev)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    E, mx = s.run_monitored(steps, every)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ok = bool(np.all(np.diff(E) <= 1e-14 * np.abs(E[:-1])) and mx.max() <= 1 + 4 * 2.0 ** -53)
+    if k == ace.ACE_KERNEL_RESIDENT:  # the whole monitored run is one launch
+        per_launch, launches = steps, 1
+    else:
+        launches = launches_in(steps, every, per_launch)
+    r = {"solver": s if keep else None, "phi0": phi0, "phi0_dev": phi0_dev if keep else None,
+         "n": float(s.total), "steps": steps, "wall": wall, "gpu_ms": gpu_ms,
+         "kernel": kernel_name(ace, w.d, k), "per_launch": per_launch,
+         "launches": launches, "plane_chunk": s.get_plane_chunk(),
+         "tuning": tuning, "E": E, "mx": mx, "theorems_hold": ok}
+    if not keep:
+        s.close()
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--workload", default="3d", choices=["3d", "2d", "1d"],
+                    help="the timed workload (default: the 3D 512^3 benchmark)")
+    ap.add_argument("--steps", type=int, default=0, help="timed steps (default: the workload's)")
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--every", type=int, default=100)
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the CPU baseline and the adjoint/batched side metrics")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+                    help="skip the CPU baseline and the adjoint/batched/other-workload side metrics")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="CPU-baseline sample length per leg (all threads, one thread)")
     ap.add_argument("--kernel", default="auto", choices=["auto", "march", "tblock", "direct"],
                     help="step kernel (auto = the library's choice)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the library's autotuner (kernel and plane-chunk choice)")
+    ap.add_argument("--plane-chunk", type=int, default=-1, metavar="P",
+                    help="fix the 3D blocked kernel's planes per workgroup, 0 = persistent grid "
+                         "(skips the autotuner)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="REPS",
                     help="only copy a 1 GiB device buffer REPS times (a plain copy kernel of "
                          "known size, for scaling HBM counters) and report its bandwidth")
@@ -188,89 +291,56 @@ def main():
                           "avg_ms": ms, "GBps_read_plus_write": 16 * n / ms / 1e6}))
         return
 
-    w = inputs.W3D
-    s = ace.Solver(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
-    s.use_torch_stream()
-    kid = {"auto": ace.ACE_KERNEL_AUTO, "march": ace.ACE_KERNEL_MARCH,
-           "tblock": ace.ACE_KERNEL_TBLOCK, "direct": ace.ACE_KERNEL_DIRECT}[args.kernel]
-    s.set_kernel(kid)
-    kernel, per_launch = s.get_kernel()
-    kname = {ace.ACE_KERNEL_MARCH: "k_march3d", ace.ACE_KERNEL_TBLOCK: "k_tblock3d",
-             ace.ACE_KERNEL_DIRECT: "k_step_direct"}.get(kernel, str(kernel))
-    coords = [s.coords(a) for a in range(w.d)]
-    phi0 = inputs.initial_field(w, s.shape, coords)
-    phi0_dev = torch.tensor(phi0, device="cuda")
-    s.set_phi0(phi0_dev)
-    print(f"[bench] {w.name}: shape {s.shape}, params {s.params['kappa']:.7g} kappa, "
-          f"{s.params['newton_iters']} Newton steps", file=sys.stderr, flush=True)
-
-    tuning = None
-    if args.kernel == "auto" and not args.no_autotune:
-        tuning = json.loads(s.autotune(20))
-        kernel, per_launch = s.get_kernel()
-        kname = {ace.ACE_KERNEL_MARCH: "k_march3d", ace.ACE_KERNEL_TBLOCK: "k_tblock3d",
-                 ace.ACE_KERNEL_DIRECT: "k_step_direct"}.get(kernel, str(kernel))
-        print(f"[bench] autotuner choice: {tuning['choice']}", file=sys.stderr, flush=True)
-    # warmup (also loads every kernel variant used below)
-    s.set_phi0(phi0_dev)
-    s.run_monitored(args.warmup, args.every)
-    torch.cuda.synchronize()
-
-    s.set_phi0(phi0_dev)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record()
-    E, mx = s.run_monitored(args.steps, args.every)
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    n = float(s.total)
-    updates = n * args.steps
-    value = updates / wall
-    print(f"[bench] {args.steps} steps in {wall:.3f} s wall, {gpu_ms:.1f} ms on the stream; "
-          f"max-norm {mx.max():.6f}, energy {E[0]:.6g} -> {E[-1]:.6g}", file=sys.stderr, flush=True)
-    if not (np.all(np.diff(E) <= 1e-14 * np.abs(E[:-1])) and mx.max() <= 1 + 4 * 2.0 ** -53):
+    w = {"3d": inputs.W3D, "2d": inputs.W2D, "1d": inputs.W1D}[args.workload]
+    steps = args.steps or w.steps
+    print(f"[bench] {w.name}: {steps} steps", file=sys.stderr, flush=True)
+    r = timed_workload(ace, torch, w, args.kernel, args.plane_chunk, not args.no_autotune, steps,
+                       args.warmup, args.every, keep=True)
+    s = r["solver"]
+    n = r["n"]
+    value = n * steps / r["wall"]
+    print(f"[bench] {steps} steps in {r['wall']:.3f} s wall, {r['gpu_ms']:.1f} ms on the stream; "
+          f"{r['kernel']} x{r['per_launch']}; max-norm {r['mx'].max():.6f}, energy "
+          f"{r['E'][0]:.6g} -> {r['E'][-1]:.6g}", file=sys.stderr, flush=True)
+    if not r["theorems_hold"]:
         print("[bench] WARNING: maximum principle or energy decay violated", file=sys.stderr)
 
     # roofline of the step kernel: average launch time over the timed region
-    # (the region holds steps/per_launch step launches plus one monitor
-    # reduction per 100 steps, a few microseconds each)
-    launches = -(-args.steps // per_launch)
-    avg_launch_s = gpu_ms / 1e3 / launches
-    bytes_per_launch = BYTES_PER_UPDATE * n * per_launch
+    # (the region holds the step launches plus one monitor reduction per
+    # monitor interval, a few microseconds each)
+    avg_launch_s = r["gpu_ms"] / 1e3 / r["launches"]
+    bytes_per_launch = BYTES_PER_UPDATE * n * r["per_launch"]
     achieved = bytes_per_launch / avg_launch_s
-    traffic = measured_traffic(kname)
+    traffic = measured_traffic(r["kernel"], r["plane_chunk"])
     roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": achieved / HBM_PEAK, "traffic": traffic,
-            "kernel": f"{kname} ({per_launch} step(s) per launch)",
+            "kernel": f"{r['kernel']} ({r['per_launch']} step(s) per launch)",
             "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_launch_s * 1e6}
+    if w.d == 3:
+        roof["plane_chunk"] = r["plane_chunk"]
 
     out = {
         "metric": "FP64 grid-pt updates/s + % HBM roofline; adjoint cost ratio; batched vs looped",
         "value": value,
         "unit": "grid-pt updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "ms_per_step": r["wall"] * 1e3 / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "3D Allen-Cahn RLB-MIE-FD step, periodic, 512^3 nodes on (0,1)^3, "
-                               "eps 0.02, dt 5e-4, tanh sphere r 0.3 + U[-0.01,0.01] noise, "
-                               "energy + max-norm fused every 100 steps",
-                   "nodes": int(n), "monitor_every": args.every},
+        "config": {"workload": WORKLOAD_DESC[args.workload], "nodes": int(n),
+                   "monitor_every": args.every},
         "roofline": roof,
     }
-    if tuning is not None:
-        out["autotune"] = tuning["choice"]
-    if not args.no_extras:
+    if r["tuning"] is not None:
+        out["autotune"] = r["tuning"]["choice"]
+    if not args.no_extras and w.d == 3:
         # the explicit comparison scheme (Remark 2) on the same workload and kernel
+        phi0_dev = r["phi0_dev"]
         s.set_scheme(ace.ACE_SCHEME_FEX)
         s.set_phi0(phi0_dev)
         s.step(100)
@@ -280,19 +350,34 @@ def main():
         f1 = torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         f0.record()
-        s.step(args.steps)
+        s.step(steps)
         f1.record()
         torch.cuda.synchronize()
         fwall = time.perf_counter() - t0
-        favg = f0.elapsed_time(f1) / 1e3 / launches
-        out["fex_scheme"] = {"value": n * args.steps / fwall, "unit": "grid-pt updates/s",
+        favg = f0.elapsed_time(f1) / 1e3 / -(-steps // r["per_launch"])
+        out["fex_scheme"] = {"value": n * steps / fwall, "unit": "grid-pt updates/s",
                              "roofline_frac": bytes_per_launch / favg / HBM_PEAK,
                              "kernel": roof["kernel"]}
     s.close()
-    del phi0_dev
+    phi0 = r["phi0"]
+    del r
     torch.cuda.empty_cache()
 
     if not args.no_extras:
+        for name, ow in (("workload_2d", inputs.W2D), ("workload_1d", inputs.W1D)):
+            if ow is w:
+                continue
+            try:
+                o = timed_workload(ace, torch, ow, warmup=args.warmup, every=args.every)
+                upd = o["n"] * o["steps"]
+                out[name] = {"value": upd / o["wall"], "unit": "grid-pt updates/s",
+                             "ms_per_step": o["wall"] * 1e3 / o["steps"], "steps": o["steps"],
+                             "kernel": f"{o['kernel']} ({o['per_launch']} step(s) per launch)",
+                             "algorithmic_hbm_frac": BYTES_PER_UPDATE * upd / (o["gpu_ms"] / 1e3)
+                             / HBM_PEAK,
+                             "theorems_hold": o["theorems_hold"]}
+            except Exception as e:  # report, never hide
+                out[name] = {"error": repr(e)}
         try:
             ratio, fwd_ms, bwd_ms = adjoint_ratio(ace, torch)
             out["adjoint_cost_ratio"] = ratio
@@ -307,7 +392,7 @@ def main():
         except Exception as e:
             out["batched_speedup"] = None
             out["batched_error"] = repr(e)
-        out["cpu_baseline"] = cpu_baseline(w, phi0, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(w, phi0, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

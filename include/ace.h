@@ -56,7 +56,8 @@ extern "C" {
 #define ACE_KERNEL_DIRECT 1  /* one thread per node, neighbours from cache    */
 #define ACE_KERNEL_MARCH 2   /* 3D: tiles marching along axis 0, LDS planes    */
 #define ACE_KERNEL_RESIDENT 3 /* whole field in LDS, many steps per launch    */
-#define ACE_KERNEL_TBLOCK 4  /* 3D: temporal blocking, 2 steps per launch      */
+#define ACE_KERNEL_TBLOCK 4  /* temporal blocking: 3D 2 steps per launch,
+                                2D 1..12 steps per launch                     */
 
 /* ---- schemes (ace_set_scheme) ------------------------------------------ */
 #define ACE_SCHEME_RLB_MIE 0 /* the paper's scheme (default)                   */
@@ -142,10 +143,22 @@ int ace_set_graph_launches(ace_solver *s, int64_t launches);
 int ace_set_scheme(ace_solver *s, int scheme);
 
 /* Kernel choice for ace_step (ACE_KERNEL_*) and its temporal depth (steps
- * per launch; 0 = default; ACE_KERNEL_TBLOCK accepts 0 or 2).  A choice that
- * does not apply to the handle's dimension or size falls back to
- * ACE_KERNEL_DIRECT.  Every choice computes the same result bit for bit. */
+ * per launch; 0 = default).  ACE_KERNEL_TBLOCK accepts 0 or 2 in 3D and
+ * 0..12 in 2D.  A choice that does not apply to the handle's dimension or
+ * size falls back to ACE_KERNEL_DIRECT.  Every choice computes the same
+ * result bit for bit.  Error: ACE_E_ARG for an unknown kernel or depth. */
 int ace_set_kernel(ace_solver *s, int kernel, int depth);
+
+/* Planes of axis 0 per workgroup of the 3D temporally blocked kernel
+ * (launch shape only; results are unchanged).  0 selects a persistent grid:
+ * as many workgroups as fit on the device at once, each marching an even
+ * share of all (tile, plane) pairs.  ace_autotune sets it; this fixes it,
+ * e.g. to take hardware counters of one launch shape.  planes = 0 or in
+ * [8, 4096]; ACE_E_ARG otherwise or when d != 3. */
+int ace_set_plane_chunk(ace_solver *s, int planes);
+
+/* The plane chunk the 3D temporally blocked kernel will use. */
+int ace_get_plane_chunk(const ace_solver *s, int *planes);
 
 /* The kernel ace_step will actually use (after ACE_KERNEL_AUTO, the autotuned
  * choice and fallbacks are resolved) and its steps per launch. */

@@ -31,6 +31,7 @@
  *    D(x)I(x)I (the printed first and last terms coincide).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -413,4 +414,14 @@ double oracle_phase_volume(int d, const long *M, double dx, const double *phi)
     neumaier_t acc = {0, 0};
     for (long i = 0; i < n; ++i) nsum_add(&acc, 0.5 * (1.0 + phi[i]));
     return pow(dx, d) * nsum_get(&acc);
+}
+
+/* Threads the parallel loops above use (for timing the CPU baseline only;
+ * results do not depend on it, since every parallel loop is a pointwise map
+ * and the sums run serially). Returns the previous maximum. */
+int oracle_set_threads(int n)
+{
+    int prev = omp_get_max_threads();
+    if (n > 0) omp_set_num_threads(n);
+    return prev;
 }

@@ -63,8 +63,16 @@ def lib():
         L.oracle_adjoint.argtypes = [ctypes.c_int, _L, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                      _D, ctypes.c_long, _D, _D, _D]
         L.oracle_adjoint.restype = ctypes.c_int
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n):
+    """Threads of the oracle's parallel loops (0 leaves them); returns the
+    previous maximum.  Results do not depend on it."""
+    return lib().oracle_set_threads(int(n))
 
 
 def _dp(a):

@@ -69,6 +69,8 @@ _SIGS = {
     "ace_set_stream": (ctypes.c_int, [_vp, _vp]),
     "ace_bind_fields": (ctypes.c_int, [_vp, _vp, _vp]),
     "ace_set_kernel": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    "ace_set_plane_chunk": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "ace_get_plane_chunk": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
     "ace_set_eps": (ctypes.c_int, [_vp, _dbl]),
     "ace_set_scheme": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ace_set_graph_launches": (ctypes.c_int, [_vp, _i64]),
@@ -221,6 +223,14 @@ class Solver:
 
     def set_kernel(self, kernel, depth=0):
         _check(lib().ace_set_kernel(self._h, int(kernel), int(depth)), "ace_set_kernel")
+
+    def set_plane_chunk(self, planes):
+        _check(lib().ace_set_plane_chunk(self._h, int(planes)), "ace_set_plane_chunk")
+
+    def get_plane_chunk(self):
+        p = ctypes.c_int()
+        _check(lib().ace_get_plane_chunk(self._h, ctypes.byref(p)), "ace_get_plane_chunk")
+        return p.value
 
     def get_kernel(self):
         """(kernel id, steps per launch) that ace_step will use."""

@@ -220,7 +220,7 @@ struct ace_solver {
     int64_t steps = 0;
     int kernel = ACE_KERNEL_AUTO;
     int depth = 0;
-    int zchunk = 32;  // planes per workgroup of the 3D temporal-blocking kernel
+    int zchunk = 32;  // planes per workgroup of the 3D temporal-blocking kernel (0: persistent)
     int depth2 = 4;   // steps per launch of the 2D temporal-blocking kernel
     int tuned_kernel = 0;  // autotuned choice for ACE_KERNEL_AUTO (0: none)
     // reverse mode
@@ -444,7 +444,7 @@ void load_tuning(ace_solver *s)
                    &zc, &k2, &ms) != 9)
             continue;
         if (d == s->p.d && bc == s->p.bc && m0 == s->p.M[0] && m1 == s->p.M[1] && m2 == s->p.M[2] &&
-            k >= ACE_KERNEL_DIRECT && k <= ACE_KERNEL_TBLOCK && zc >= TBLOCK_MIN_ZCHUNK && k2 >= 1 &&
+            k >= ACE_KERNEL_DIRECT && k <= ACE_KERNEL_TBLOCK && (zc == 0 || zc >= TBLOCK_MIN_ZCHUNK) && k2 >= 1 &&
             k2 <= tblock2d_max_depth()) {
             s->tuned_kernel = k;
             s->zchunk = zc;
@@ -650,6 +650,21 @@ int ace_set_kernel(ace_solver *s, int kernel, int depth)
     return ACE_OK;
 }
 
+int ace_set_plane_chunk(ace_solver *s, int planes)
+{
+    if (!s || s->p.d != 3 || (planes != 0 && (planes < TBLOCK_MIN_ZCHUNK || planes > 4096)))
+        return ACE_E_ARG;
+    s->zchunk = planes;
+    return ACE_OK;
+}
+
+int ace_get_plane_chunk(const ace_solver *s, int *planes)
+{
+    if (!s || !planes) return ACE_E_ARG;
+    *planes = s->zchunk;
+    return ACE_OK;
+}
+
 int ace_get_kernel(const ace_solver *s, int *kernel, int *steps_per_launch)
 {
     if (!s || !kernel) return ACE_E_ARG;
@@ -796,7 +811,7 @@ int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap)
     if (s->p.total <= RESIDENT_MAX) cands.push_back({ACE_KERNEL_RESIDENT, s->zchunk, s->depth2});
     if (march_supported(s->shape)) cands.push_back({ACE_KERNEL_MARCH, s->zchunk, s->depth2});
     if (s->p.d == 3 && tblock_supported(s->shape))
-        for (int zc : {16, 24, 32, 40, 48, 64, 128})
+        for (int zc : {0, 16, 24, 32, 40, 48, 64, 128})  // 0: persistent grid
             if (zc <= std::max<int64_t>(s->shape.M0, 16)) cands.push_back({ACE_KERNEL_TBLOCK, zc, s->depth2});
     if (s->p.d == 2 && tblock2d_supported(s->shape))
         for (int k2 : {1, 2, 4, 6, 8, 12})

@@ -137,6 +137,17 @@ __device__ __forceinline__ double outside(double self, double wrap)
 }
 
 // NaN-propagating maximum (fmax drops NaN).
+// Workgroups are dealt to the 8 XCDs round-robin: block b runs on XCD b % 8.
+// This renumbering gives each XCD one contiguous range of logical tiles, so
+// neighbouring tiles, which read each other's edge rows, share that XCD's L2.
+// It is a bijection on [0, nblk) for every nblk: with nblk = 8q + r, XCDs
+// 0..r-1 take q+1 tiles and the others q.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nblk)
+{
+    const int64_t q = nblk >> 3, r = nblk & 7, x = b & 7, k = b >> 3;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
 __device__ __forceinline__ double nan_max(double a, double b)
 {
     if (a != a) return a;

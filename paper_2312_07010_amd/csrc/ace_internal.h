@@ -65,7 +65,9 @@ bool march_supported(const Shape &s);
 int64_t march_partials_needed(const Shape &s);
 
 // 3D: two steps per launch (temporal blocking); same partials contract (the
-// monitors are those of the input field).  zchunk = planes per workgroup.
+// monitors are those of the input field).  zchunk = planes per workgroup, or
+// 0 for a persistent grid in which each workgroup marches an even share of
+// all tile-planes.
 hipError_t launch_step_tblock2(const Shape &s, const StepCoef &c, const double *in,
                                double *out, double *partials, int64_t *nparts, int zchunk,
                                hipStream_t st);

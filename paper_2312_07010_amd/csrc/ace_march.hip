@@ -69,13 +69,7 @@ __global__ __launch_bounds__(NT) void k_march3d(Shape s, StepCoef c, const doubl
     __shared__ double red[3 * (NT / 64)];
     (void)nchunks;
 
-    // XCD-aware numbering: workgroups are dealt to the 8 XCDs round-robin, so
-    // block b runs on XCD b % 8.  Giving each XCD a contiguous range of tiles
-    // puts neighbouring tiles (which read each other's edge rows) in the same
-    // L2.  Only used when the block count divides evenly (a bijection).
-    const int64_t nblk = gridDim.x;
-    const int64_t b = blockIdx.x;
-    const int64_t t = (nblk % 8 == 0) ? (b % 8) * (nblk / 8) + b / 8 : b;
+    const int64_t t = xcd_tile(blockIdx.x, gridDim.x);  // XCD-aware numbering
     const int64_t ntile = (int64_t)tiles_x * tiles_y;
     const int tile_xy = (int)(t % ntile);
     const int chunk = (int)(t / ntile);

@@ -39,6 +39,7 @@ constexpr int NT = RX * TRW;     // 512 threads
 constexpr int LW = RX + 2;       // LDS plane with a zero pad all around
 constexpr int LH = RH + 2;
 constexpr int LP = LW * LH;
+constexpr int64_t PERSIST_MIN = 16;  // least tile-planes per persistent workgroup
 
 template <int BC>
 __device__ __forceinline__ int64_t map_coord2(int64_t c, int64_t n)
@@ -66,13 +67,20 @@ __device__ __forceinline__ int64_t plane_base2(const Shape &s, int64_t z)
     return mz < 0 ? -1 : mz * s.M1 * s.M2;
 }
 
+// Mapped plane bases and row offsets are never negative for Neumann and
+// periodic, so those loads are unconditional (no exec-masked branches in the
+// march); Dirichlet marks the zero nodes outside the domain with -1.
+template <int BC>
 __device__ __forceinline__ double load_at2(const double *__restrict__ in, int64_t base, int64_t off)
 {
+    if (BC != BC_HD) return in[base + off];
     return (base < 0 || off < 0) ? 0.0 : in[base + off];
 }
 
 template <int BC, bool MON, int NIT>
-__global__ __launch_bounds__(NT) void k_tblock3d(Shape s, StepCoef c, const double *__restrict__ in,
+// amdgpu_waves_per_eu(4) caps the kernel at 128 VGPRs, so two 512-thread
+// workgroups (LDS 72 KB each) share a CU.
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_tblock3d(Shape s, StepCoef c, const double *__restrict__ in,
                                                  double *__restrict__ out,
                                                  double *__restrict__ partials, int tiles_x,
                                                  int tiles_y, int zchunk)
@@ -81,23 +89,37 @@ __global__ __launch_bounds__(NT) void k_tblock3d(Shape s, StepCoef c, const doub
     __shared__ double L1[2 * LP];
     __shared__ double red[3 * (NT / 64)];
 
-    // XCD-aware numbering (block b runs on XCD b % 8; see the one-step kernel)
-    const int64_t nblk = gridDim.x;
-    const int64_t b = blockIdx.x;
-    const int64_t t = (nblk % 8 == 0) ? (b % 8) * (nblk / 8) + b / 8 : b;
+    const int64_t t = xcd_tile(blockIdx.x, gridDim.x);  // XCD-aware numbering
     const int64_t ntile = (int64_t)tiles_x * tiles_y;
-    const int tile_xy = (int)(t % ntile);
-    const int chunk = (int)(t / ntile);
-    const int tile_x = tile_xy % tiles_x;
-    const int tile_y = tile_xy / tiles_x;
-
+    // The workgroup's share of the tile-planes, numbered tile-major
+    // (tile * M0 + plane): one chunk of one tile, or (zchunk = 0, a
+    // persistent grid) an even share of all of them, which it marches as one
+    // segment per tile it touches.
+    int64_t lo, hi;
+    if (zchunk > 0) {
+        const int64_t tile = t % ntile, chunk = t / ntile;
+        lo = tile * s.M0 + chunk * zchunk;
+        hi = tile * s.M0 + ((chunk + 1) * zchunk < s.M0 ? (chunk + 1) * zchunk : s.M0);
+    } else {
+        const int64_t P = ntile * s.M0;
+        lo = t * P / gridDim.x;
+        hi = (t + 1) * P / gridDim.x;
+    }
     const int tx = threadIdx.x & (RX - 1);
     const int tr = threadIdx.x / RX;
+    const int64_t PS = s.M1 * s.M2;
+    MonAcc m;
+    mon_zero(m);
+
+    while (lo < hi) {
+    const int64_t tile_xy = lo / s.M0;
+    const int64_t z0 = lo - tile_xy * s.M0;
+    const int64_t z1 = (z0 + (hi - lo) < s.M0) ? z0 + (hi - lo) : s.M0;
+    lo += z1 - z0;
+    const int tile_x = (int)(tile_xy % tiles_x);
+    const int tile_y = (int)(tile_xy / tiles_x);
     const int64_t yr0 = (int64_t)tile_y * OY - 2;  // global row of region row 0
     const int64_t xg = (int64_t)tile_x * OX - 2 + tx;
-    const int64_t z0 = (int64_t)chunk * zchunk;
-    const int64_t z1 = (z0 + zchunk < s.M0) ? z0 + zchunk : s.M0;
-    const int64_t PS = s.M1 * s.M2;
 
     for (int i = threadIdx.x; i < 2 * LP; i += NT) {
         L0[i] = 0.0;
@@ -139,10 +161,10 @@ __global__ __launch_bounds__(NT) void k_tblock3d(Shape s, StepCoef c, const doub
         const int64_t bC = plane_base2<BC>(s, z0), bD = plane_base2<BC>(s, z0 + 1);
 #pragma unroll
         for (int r = 0; r < RYT; ++r) {
-            q0[r] = load_at2(in, bA, off[r]);
-            q1[r] = load_at2(in, bB, off[r]);
-            q2[r] = load_at2(in, bC, off[r]);
-            q3[r] = load_at2(in, bD, off[r]);
+            q0[r] = load_at2<BC>(in, bA, off[r]);
+            q1[r] = load_at2<BC>(in, bB, off[r]);
+            q2[r] = load_at2<BC>(in, bC, off[r]);
+            q3[r] = load_at2<BC>(in, bD, off[r]);
         }
     }
     __syncthreads();  // zero pads written before the first staging
@@ -161,8 +183,6 @@ __global__ __launch_bounds__(NT) void k_tblock3d(Shape s, StepCoef c, const doub
         w1[r] = 0.0;
         w2[r] = 0.0;
     }
-    MonAcc m;
-    mon_zero(m);
     int bl0 = 0, bl1 = 0;
     int64_t zc = z0 - 1;
     // rows a wavefront can skip: level 1 is needed on region rows 1..RH-2,
@@ -204,6 +224,15 @@ __global__ __launch_bounds__(NT) void k_tblock3d(Shape s, StepCoef c, const doub
                 m.mx = nan_max(m.mx, fabs(p));
             }
         }
+        // --- B: next level-0 plane zc+3 into the slot A just freed (Q0).  Issued
+        // before C's stores so the loads have C, the staging and the barrier
+        // to arrive in.  Past the last plane the segment needs (z1+1) the
+        // load repeats that plane (unused). ---
+        {
+            const int64_t bn = plane_base2<BC>(s, (zc + 3 <= z1 + 1) ? zc + 3 : z1 + 1);
+#pragma unroll
+            for (int r = 0; r < RYT; ++r) Q0[r] = load_at2<BC>(in, bn, off[r]);
+        }
         // --- C: level 2 of plane zc-1 on the tile ---
         if (zc >= z0 + 1) {
             const int64_t zo = zc - 1;
@@ -227,10 +256,7 @@ __global__ __launch_bounds__(NT) void k_tblock3d(Shape s, StepCoef c, const doub
             }
         }
         if (zc >= z1) return true;
-        // --- next level-0 plane zc+3 into the dead slot Q0; stage plane zc+1 ---
-        const int64_t bn = (zc + 3 <= z1 + 1) ? plane_base2<BC>(s, zc + 3) : -1;
-#pragma unroll
-        for (int r = 0; r < RYT; ++r) Q0[r] = load_at2(in, bn, off[r]);
+        // --- stage plane zc+1 ---
         bl0 ^= 1;
         bl1 ^= 1;
 #pragma unroll
@@ -257,6 +283,8 @@ __global__ __launch_bounds__(NT) void k_tblock3d(Shape s, StepCoef c, const doub
         if (body(qc, qd, qa, qb, w1, w2, w0)) break;
         if (body(qd, qa, qb, qc, w2, w0, w1)) break;
     }
+    __syncthreads();  // every wavefront is done with the LDS planes of this segment
+    }
     if (MON) block_reduce_store(m, red, partials + 3 * t);
 }
 
@@ -269,37 +297,87 @@ bool tblock_supported(const Shape &s)
 
 int64_t tblock_partials_needed(const Shape &s, int zchunk)
 {
-    return ((s.M2 + OX - 1) / OX) * ((s.M1 + OY - 1) / OY) * ((s.M0 + zchunk - 1) / zchunk);
+    const int64_t tiles = ((s.M2 + OX - 1) / OX) * ((s.M1 + OY - 1) / OY);
+    if (zchunk <= 0) return std::max<int64_t>(1, std::min<int64_t>(8192, tiles * s.M0 / PERSIST_MIN));
+    return tiles * ((s.M0 + zchunk - 1) / zchunk);
 }
 
+namespace {
+
+// Workgroups of one kernel instance that fit on the device at once (cached
+// per device and instance; 0 if the query fails).
+template <int BC, bool MON, int NIT>
+int64_t resident_blocks()
+{
+    static int64_t cache[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (cache[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tblock3d<BC, MON, NIT>, NT, 0) !=
+                hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        cache[dev] = (int64_t)std::max(per_cu, 1) * cus;
+    }
+    return cache[dev];
+}
+
+template <int BC, bool MON, int NIT>
+hipError_t launch_tb(const Shape &s, const StepCoef &c, const double *in, double *out,
+                     double *partials, int64_t *nparts, int zchunk, hipStream_t st)
+{
+    const int tiles_x = (int)((s.M2 + OX - 1) / OX);
+    const int tiles_y = (int)((s.M1 + OY - 1) / OY);
+    int64_t nblk;
+    if (zchunk > 0) {
+        nblk = (int64_t)tiles_x * tiles_y * ((s.M0 + zchunk - 1) / zchunk);
+    } else {
+        const int64_t res = resident_blocks<BC, MON, NIT>();
+        if (res <= 0) return hipErrorInvalidValue;
+        nblk = std::min<int64_t>(res, tblock_partials_needed(s, 0));
+    }
+    if (nparts) *nparts = nblk;
+    hipLaunchKernelGGL((k_tblock3d<BC, MON, NIT>), dim3((unsigned)nblk), dim3(NT), 0, st, s, c, in,
+                       out, partials, tiles_x, tiles_y, zchunk);
+    return hipGetLastError();
+}
+
+template <int BC, int NIT>
+hipError_t launch_tb_mon(const Shape &s, const StepCoef &c, const double *in, double *out,
+                         double *partials, int64_t *nparts, int zchunk, hipStream_t st)
+{
+    return partials ? launch_tb<BC, true, NIT>(s, c, in, out, partials, nparts, zchunk, st)
+                    : launch_tb<BC, false, NIT>(s, c, in, out, partials, nparts, zchunk, st);
+}
+
+template <int BC>
+hipError_t launch_tb_nit(const Shape &s, const StepCoef &c, const double *in, double *out,
+                         double *partials, int64_t *nparts, int zchunk, hipStream_t st)
+{
+    switch (c.nit) {
+    case 1: return launch_tb_mon<BC, 1>(s, c, in, out, partials, nparts, zchunk, st);
+    case 2: return launch_tb_mon<BC, 2>(s, c, in, out, partials, nparts, zchunk, st);
+    case 3: return launch_tb_mon<BC, 3>(s, c, in, out, partials, nparts, zchunk, st);
+    default: return launch_tb_mon<BC, 0>(s, c, in, out, partials, nparts, zchunk, st);
+    }
+}
+
+}  // namespace
+
+// zchunk > 0: one workgroup per (tile, chunk of zchunk planes); zchunk = 0:
+// a persistent grid of the workgroups that fit at once, each marching an
+// even share of the tile-planes (at least PERSIST_MIN of them).
 hipError_t launch_step_tblock2(const Shape &s, const StepCoef &c, const double *in, double *out,
                                double *partials, int64_t *nparts, int zchunk, hipStream_t st)
 {
-    if (!tblock_supported(s) || zchunk < 1) return hipErrorInvalidValue;
-    const int tiles_x = (int)((s.M2 + OX - 1) / OX);
-    const int tiles_y = (int)((s.M1 + OY - 1) / OY);
-    const int nchunks = (int)((s.M0 + zchunk - 1) / zchunk);
-    const int64_t nblk = (int64_t)tiles_x * tiles_y * nchunks;
-    if (nparts) *nparts = nblk;
-#define ACE_TB_N(BB, NN)                                                                        \
-    if (partials)                                                                               \
-        hipLaunchKernelGGL((k_tblock3d<BB, true, NN>), dim3((unsigned)nblk), dim3(NT), 0, st, s,  \
-                           c, in, out, partials, tiles_x, tiles_y, zchunk);                     \
-    else                                                                                        \
-        hipLaunchKernelGGL((k_tblock3d<BB, false, NN>), dim3((unsigned)nblk), dim3(NT), 0, st,   \
-                           s, c, in, out, partials, tiles_x, tiles_y, zchunk);                  \
-    return hipGetLastError();
-#define ACE_TB(BB)                                        \
-    if (s.bc == BB) {                                     \
-        if (c.nit == 1) { ACE_TB_N(BB, 1) }               \
-        if (c.nit == 2) { ACE_TB_N(BB, 2) }               \
-        if (c.nit == 3) { ACE_TB_N(BB, 3) }               \
-        ACE_TB_N(BB, 0)                                   \
+    if (!tblock_supported(s) || zchunk < 0) return hipErrorInvalidValue;
+    switch (s.bc) {
+    case BC_HN: return launch_tb_nit<BC_HN>(s, c, in, out, partials, nparts, zchunk, st);
+    case BC_HD: return launch_tb_nit<BC_HD>(s, c, in, out, partials, nparts, zchunk, st);
+    case BC_P: return launch_tb_nit<BC_P>(s, c, in, out, partials, nparts, zchunk, st);
+    default: return hipErrorInvalidValue;
     }
-    ACE_TB(BC_HN) ACE_TB(BC_HD) ACE_TB(BC_P)
-#undef ACE_TB
-#undef ACE_TB_N
-    return hipErrorInvalidValue;
 }
 
 }  // namespace ace

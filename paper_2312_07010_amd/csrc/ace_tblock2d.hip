@@ -63,7 +63,7 @@ template <int BC>
 __device__ __forceinline__ Geo make_geo(const Shape &s, int K, int tiles_x)
 {
     Geo g;
-    const int tile = blockIdx.x;
+    const int tile = (int)xcd_tile(blockIdx.x, gridDim.x);  // XCD-aware numbering
     const int tx = threadIdx.x & (BX - 1);
     const int oy = BH - 2 * K, ox = BX - 2 * K;
     g.y0r = (int64_t)(tile / tiles_x) * oy - K;

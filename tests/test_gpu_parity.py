@@ -228,3 +228,55 @@ def test_2d_blocked_ragged_rectangles(ace, orc, bc, shape):
         E, _ = s.run_monitored(25, 5)
         assert np.array_equal(s.get_phi(), ref), depth
         np.testing.assert_allclose(E, Ew, rtol=1e-12)
+
+
+@pytest.mark.parametrize("planes", [0, 8, 13, 40])
+@pytest.mark.parametrize("bc", [0, 1, 2])
+@pytest.mark.parametrize("N", [(21, 35, 129), (70, 61, 130)])
+def test_3d_blocked_launch_shapes(ace, orc, bc, N, planes):
+    """The 3D two-step kernel at several plane chunks and as a persistent grid
+    (planes = 0), where one workgroup marches several segments that cross
+    tile boundaries: same result as the oracle, and bit for bit the one-step
+    kernel's, monitors included."""
+    dx = 1.0 / 64
+    R = [n * dx for n in N]
+    dt = 1e-3
+    eps = math.sqrt(0.12 * dx * dx / dt)
+    s = ace.Solver(3, list(N), [0.0] * 3, R, eps, dt, bc)
+    p = orc.Problem(3, list(N), [0.0] * 3, R, eps, dt, bc)
+    phi0 = np.random.default_rng(5 + bc + planes).uniform(-1, 1, p.shape)
+    want, Ew, mw = p.run(phi0, 7, 3)
+    s.set_kernel(ace.ACE_KERNEL_DIRECT)
+    s.set_phi0(phi0)
+    Ed, md = s.run_monitored(7, 3)
+    ref = s.get_phi()
+    s.set_kernel(ace.ACE_KERNEL_TBLOCK)
+    s.set_plane_chunk(planes)
+    assert s.get_plane_chunk() == planes
+    s.set_phi0(phi0)
+    E, m = s.run_monitored(7, 3)
+    got = s.get_phi()
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(E, Ew, rtol=1e-12)
+    np.testing.assert_allclose(m, mw, rtol=0, atol=1e-13)
+    assert np.array_equal(got, ref)
+    np.testing.assert_allclose(E, Ed, rtol=1e-13)
+
+
+def test_3d_persistent_grid_fills_the_device(ace, orc):
+    """A field large enough that the persistent grid uses every resident
+    workgroup slot, each marching segments of two or more tiles."""
+    N = [256, 128, 256]
+    dt = 1e-3
+    dx = 1.0 / 256
+    eps = math.sqrt(0.1 * dx * dx / dt)
+    R = [n * dx for n in N]
+    s = ace.Solver(3, N, [0.0] * 3, R, eps, dt, "P")
+    p = orc.Problem(3, N, [0.0] * 3, R, eps, dt, "P")
+    phi0 = np.random.default_rng(9).uniform(-1, 1, p.shape)
+    want, _, _ = p.run(phi0, 4)
+    s.set_kernel(ace.ACE_KERNEL_TBLOCK)
+    s.set_plane_chunk(0)
+    s.set_phi0(phi0)
+    s.step(4)
+    np.testing.assert_allclose(s.get_phi(), want, rtol=0, atol=1e-13)
