@@ -416,6 +416,111 @@ double oracle_phase_volume(int d, const long *M, double dx, const double *phi)
     return pow(dx, d) * nsum_get(&acc);
 }
 
+/* ---------------------------------------------------------------------- */
+/* Mesoscopic form (Sec. 2): populations of the DdQ(2d+1) lattice          */
+/* ---------------------------------------------------------------------- */
+/*
+ * Population k = 0 rests; k = 1..d moves along +axis (k-1) and k = d+1..2d
+ * along -axis (k-d-1), with axis 0 the slowest storage axis (the paper's
+ * x_1).  Velocities c_k = +-c e, c = dx/dt.  Weights w_0 = 1 - 2 d w_1 and
+ * w_1 = ... = w_2d (Sec. 2, moment conditions).  The q = 2d+1 arrays are
+ * stored one after another: f[k * n + i].
+ */
+
+/* phi = sum_k f_k, the zeroth moment.                                     */
+void oracle_pop_moment(int d, const long *M, const double *f, double *phi)
+{
+    const long n = oracle_total(d, M);
+    const int q = 2 * d + 1;
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) {
+        double p = 0.0;
+        for (int k = 0; k < q; ++k) p = p + f[k * n + i];
+        phi[i] = p;
+    }
+}
+
+/* Equilibrium populations f_k = w_k phi (Sec. 2, equilibrium distribution). */
+void oracle_pop_equilibrium(int d, const long *M, double omega1, const double *phi,
+                            double *f)
+{
+    const long n = oracle_total(d, M);
+    const double w0 = 1.0 - 2.0 * d * omega1;
+    for (long i = 0; i < n; ++i) {
+        f[i] = w0 * phi[i];
+        for (int k = 1; k <= 2 * d; ++k) f[k * n + i] = omega1 * phi[i];
+    }
+}
+
+/* One step of the regularized evolution equation of Sec. 2 (the RLB form
+ * before summation), taken in the paper's order:
+ *   1. phi = sum_k f_k;
+ *   2. for each population, the right-hand side
+ *        RHS_k(x) = f_k^eq(x - c_k dt) + s_A w_k c_k . Pi^ne(x - c_k dt)
+ *                   + (dt/2) F_k(x, t),
+ *      with f_k^eq = w_k phi, F_k = -w_k f(phi), s_A = (1 - s)/c_s^2,
+ *      c_s^2 = 2 w_1 c^2, Pi^ne = -dt c_s^2 grad(phi)/s, and the gradient at
+ *      x - c_k dt by the first-order difference between that node and x;
+ *      out-of-range nodes take the boundary condition's value (as in the
+ *      D matrices);
+ *   3. the left-hand side summed over k is phi(t+dt) + (dt/2) f(phi(t+dt)),
+ *      so phi(t+dt) is the root of the pointwise cubic for xi = sum_k RHS_k;
+ *   4. f_k(x, t+dt) = RHS_k + (dt/2) F_k(x, t+dt).                        */
+void oracle_pop_step(int d, const long *M, int bc, double omega1, double s,
+                     double dt, double dx, const double *f, double *fout)
+{
+    const long n = oracle_total(d, M);
+    const int q = 2 * d + 1;
+    long st[3];
+    strides(d, M, st);
+    double *phi = (double *)malloc(sizeof(double) * (size_t)n);
+    oracle_pop_moment(d, M, f, phi);
+    const double c = dx / dt;
+    const double cs2 = 2.0 * omega1 * c * c;
+    const double sA = (1.0 - s) / cs2;
+    const double h = 0.5 * dt;
+    const double w0 = 1.0 - 2.0 * d * omega1;
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) {
+        double rhs[7];
+        const double p = phi[i];
+        const double fp = p * p * p - p;
+        rhs[0] = w0 * p + h * (w0 * (-fp));
+        for (int a = 0; a < d; ++a) {
+            /* k = 1 + a: c_k = +c e_a, from x - e_a dx */
+            const double lo = neighbour(phi, d, M, st, bc, i, a, -1);
+            const double pim = -dt * cs2 * ((p - lo) / dx) / s;
+            rhs[1 + a] = omega1 * lo + sA * omega1 * (c * pim) + h * (omega1 * (-fp));
+            /* k = 1 + d + a: c_k = -c e_a, from x + e_a dx */
+            const double hi = neighbour(phi, d, M, st, bc, i, a, +1);
+            const double pip = -dt * cs2 * ((hi - p) / dx) / s;
+            rhs[1 + d + a] = omega1 * hi + sA * omega1 * (-c * pip) + h * (omega1 * (-fp));
+        }
+        double xi = 0.0;
+        for (int k = 0; k < q; ++k) xi = xi + rhs[k];
+        const double th = oracle_root(xi, h);
+        const double ft = th * th * th - th;
+        for (int k = 0; k < q; ++k) {
+            const double w = (k == 0) ? w0 : omega1;
+            fout[k * n + i] = rhs[k] + h * (w * (-ft));
+        }
+    }
+    free(phi);
+}
+
+/* nsteps steps (ping-pong inside; f is overwritten with the result).     */
+void oracle_pop_run(int d, const long *M, int bc, double omega1, double s, double dt,
+                    double dx, double *f, long nsteps)
+{
+    const long n = oracle_total(d, M) * (2 * d + 1);
+    double *g = (double *)malloc(sizeof(double) * (size_t)n);
+    for (long t = 0; t < nsteps; ++t) {
+        oracle_pop_step(d, M, bc, omega1, s, dt, dx, f, g);
+        memcpy(f, g, sizeof(double) * (size_t)n);
+    }
+    free(g);
+}
+
 /* Threads the parallel loops above use (for timing the CPU baseline only;
  * results do not depend on it, since every parallel loop is a pointwise map
  * and the sums run serially). Returns the previous maximum. */

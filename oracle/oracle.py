@@ -63,6 +63,16 @@ def lib():
         L.oracle_adjoint.argtypes = [ctypes.c_int, _L, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                      _D, ctypes.c_long, _D, _D, _D]
         L.oracle_adjoint.restype = ctypes.c_int
+        L.oracle_pop_moment.argtypes = [ctypes.c_int, _L, _D, _D]
+        L.oracle_pop_moment.restype = None
+        L.oracle_pop_equilibrium.argtypes = [ctypes.c_int, _L, ctypes.c_double, _D, _D]
+        L.oracle_pop_equilibrium.restype = None
+        L.oracle_pop_step.argtypes = [ctypes.c_int, _L, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, _D, _D]
+        L.oracle_pop_step.restype = None
+        L.oracle_pop_run.argtypes = [ctypes.c_int, _L, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, _D, ctypes.c_long]
+        L.oracle_pop_run.restype = None
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_set_threads.restype = ctypes.c_int
         _lib = L
@@ -176,6 +186,44 @@ class Problem:
     def maxnorm(self, phi):
         phi = _f64(phi)
         return lib().oracle_maxnorm(phi.size, _dp(phi))
+
+    # ---- mesoscopic form (Sec. 2): 2d+1 populations per node ----
+    def default_omega1(self):
+        """The weight the paper's experiments use: 1/3, 1/5, 1/6 for d = 1, 2, 3."""
+        return {1: 1 / 3, 2: 1 / 5, 3: 1 / 6}[self.d]
+
+    def relaxation(self, omega1=None):
+        """s = omega_1 / kappa (kappa = omega_1 / s, Sec. 2)."""
+        omega1 = self.default_omega1() if omega1 is None else float(omega1)
+        return omega1 / self.kappa
+
+    def pop_equilibrium(self, phi, omega1=None):
+        omega1 = self.default_omega1() if omega1 is None else float(omega1)
+        phi = _f64(phi).reshape(self.shape)
+        f = np.empty((2 * self.d + 1,) + self.shape)
+        lib().oracle_pop_equilibrium(self.d, self._Marr, omega1, _dp(phi), _dp(f))
+        return f
+
+    def pop_moment(self, f):
+        f = _f64(f).reshape((2 * self.d + 1,) + self.shape)
+        phi = np.empty(self.shape)
+        lib().oracle_pop_moment(self.d, self._Marr, _dp(f), _dp(phi))
+        return phi
+
+    def pop_step(self, f, omega1=None):
+        omega1 = self.default_omega1() if omega1 is None else float(omega1)
+        f = _f64(f).reshape((2 * self.d + 1,) + self.shape)
+        out = np.empty_like(f)
+        lib().oracle_pop_step(self.d, self._Marr, self.bc, omega1, self.relaxation(omega1),
+                              self.dt, self.dx, _dp(f), _dp(out))
+        return out
+
+    def pop_run(self, f0, nsteps, omega1=None):
+        omega1 = self.default_omega1() if omega1 is None else float(omega1)
+        f = _f64(f0).reshape((2 * self.d + 1,) + self.shape).copy()
+        lib().oracle_pop_run(self.d, self._Marr, self.bc, omega1, self.relaxation(omega1),
+                             self.dt, self.dx, _dp(f), int(nsteps))
+        return f
 
     def adjoint(self, phi0, nsteps, lambdaT):
         """(dL/dphi0, dL/dkappa, dL/d(eps^2)) for a given dL/dphi_T."""
