@@ -250,6 +250,55 @@ int ace_forward_ckpt(ace_solver *s, const double *phi0, int where, int64_t nstep
 int ace_backward(ace_solver *s, const double *lambdaT, double *dphi0, double *deps2,
                  int where);
 
+/* ---- mesoscopic form: populations of the DdQ(2d+1) lattice -------------- */
+
+/* The regularized evolution equation of Sec. 2 before its summation over k:
+ * 2d+1 populations per node (k = 0 at rest, k = 1..d moving along +axis
+ * k-1, k = d+1..2d along -axis k-d-1; axis 0 is the slowest storage axis),
+ * with equilibrium w_k phi, source -w_k f(phi), weights w_0 = 1 - 2 d w_1,
+ * w_1 = omega1, and the non-equilibrium part regularized through the
+ * first-order gradient of phi; s = omega1 / kappa.  Summing the populations
+ * gives the FD step of ace_step (Sec. 2), so ace_pop_get_phi follows the
+ * solver's field to rounding, while the handle holds 2 (2d+1) fields instead
+ * of 2 and moves 16 (2d+1) bytes per node update instead of 16.
+ * ace_pop_create takes the ace_create arguments plus omega1 in
+ * (0, 1/(2d)] (0 selects the weights of the paper's experiments: 1/3, 1/5,
+ * 1/6 for d = 1, 2, 3).  Errors as ace_create, ACE_E_ARG for omega1;
+ * warning ACE_W_CONDITIONS as ace_create. */
+typedef struct ace_pop ace_pop;
+int ace_pop_create(int d, const int64_t N[], const double L[], const double R[], double eps,
+                   double dt, int bc, double omega1, ace_pop **out);
+int ace_pop_destroy(ace_pop *p);
+/* Stored nodes per axis, node count, populations per node (2d+1), omega1,
+ * s, and the device bytes the handle holds (any output may be NULL). */
+int ace_pop_info(const ace_pop *p, int64_t M[3], int64_t *total, int *q, double *omega1,
+                 double *s, int64_t *device_bytes);
+int ace_pop_set_stream(ace_pop *p, void *hip_stream);
+/* Kernel of ace_pop_step (every choice computes the same result bit for
+ * bit): ACE_POP_DIRECT one thread per node, phi of the node and its
+ * neighbours summed from their populations; ACE_POP_FUSED tiles marching
+ * along axis 0 that sum phi of a region into LDS and write the new
+ * populations of its interior (16 (2d+1) bytes per node update);
+ * ACE_POP_SPLIT a streaming pass writing phi = sum_k f_k, then the tiled
+ * update reading phi (16 (2d+1) + 16 bytes, aligned streams);
+ * ACE_POP_AUTO: split for d >= 2, direct for d = 1. */
+#define ACE_POP_AUTO 0
+#define ACE_POP_DIRECT 1
+#define ACE_POP_FUSED 2
+#define ACE_POP_SPLIT 3
+int ace_pop_set_kernel(ace_pop *p, int kernel);
+/* Populations at equilibrium f_k = w_k phi0 (phi0: total doubles, C order);
+ * resets the step count.  ACE_E_NONFINITE for a non-finite host value. */
+int ace_pop_set_phi0(ace_pop *p, const double *phi0, int where);
+/* All populations, (2d+1) x total doubles, population-major. */
+int ace_pop_set_populations(ace_pop *p, const double *f, int where);
+int ace_pop_get_populations(const ace_pop *p, double *f, int where);
+/* nsteps steps of the evolution equation (asynchronous on the stream). */
+int ace_pop_step(ace_pop *p, int64_t nsteps);
+/* phi = sum_k f_k (total doubles). */
+int ace_pop_get_phi(ace_pop *p, double *phi, int where);
+int64_t ace_pop_step_count(const ace_pop *p);
+
 /* ---- batches of independent instances ----------------------------------- */
 
 typedef struct ace_batch ace_batch;

@@ -24,6 +24,7 @@ ACE_HOST, ACE_DEVICE = 0, 1
 ACE_KERNEL_AUTO, ACE_KERNEL_DIRECT, ACE_KERNEL_MARCH = 0, 1, 2
 ACE_KERNEL_RESIDENT, ACE_KERNEL_TBLOCK = 3, 4
 ACE_SCHEME_RLB_MIE, ACE_SCHEME_FEX = 0, 1
+ACE_POP_AUTO, ACE_POP_DIRECT, ACE_POP_FUSED, ACE_POP_SPLIT = 0, 1, 2, 3
 
 _i64 = ctypes.c_int64
 _dbl = ctypes.c_double
@@ -100,6 +101,19 @@ _SIGS = {
     "ace_batch_set_resident_limit": (ctypes.c_int, [_vp, _i64]),
     "ace_batch_autotune": (ctypes.c_int, [_vp, _i64, ctypes.c_char_p, ctypes.c_size_t]),
     "ace_autotune": (ctypes.c_int, [_vp, _i64, ctypes.c_char_p, ctypes.c_size_t]),
+    "ace_pop_create": (ctypes.c_int, [ctypes.c_int, _P(_i64), _P(_dbl), _P(_dbl), _dbl, _dbl,
+                                      ctypes.c_int, _dbl, _P(_vp)]),
+    "ace_pop_destroy": (ctypes.c_int, [_vp]),
+    "ace_pop_info": (ctypes.c_int, [_vp, _P(_i64), _P(_i64), _P(ctypes.c_int), _P(_dbl), _P(_dbl),
+                                    _P(_i64)]),
+    "ace_pop_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "ace_pop_set_kernel": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "ace_pop_set_phi0": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "ace_pop_set_populations": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "ace_pop_get_populations": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "ace_pop_step": (ctypes.c_int, [_vp, _i64]),
+    "ace_pop_get_phi": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "ace_pop_step_count": (_i64, [_vp]),
 }
 
 _lib = None
@@ -434,3 +448,97 @@ class Batch:
         buf = ctypes.create_string_buffer(4096)
         _check(lib().ace_batch_autotune(self._h, int(trial_steps), buf, 4096), "ace_batch_autotune")
         return buf.value.decode()
+
+
+class Pop:
+    """The mesoscopic form (Sec. 2): 2d+1 populations per node under the
+    regularized evolution equation.  omega1 = 0 selects the weights of the
+    paper's experiments (1/3, 1/5, 1/6 for d = 1, 2, 3)."""
+
+    def __init__(self, d, N, L, R, eps, dt, bc, omega1=0.0):
+        bc = BC[bc] if isinstance(bc, str) else int(bc)
+        n = (_i64 * 3)(*[int(v) for v in list(N) + [1] * (3 - len(N))])
+        lo = (_dbl * 3)(*[float(v) for v in list(L) + [0.0] * (3 - len(L))])
+        hi = (_dbl * 3)(*[float(v) for v in list(R) + [1.0] * (3 - len(R))])
+        h = _vp()
+        self.status = _check(lib().ace_pop_create(int(d), n, lo, hi, float(eps), float(dt), bc,
+                                                  float(omega1), ctypes.byref(h)), "ace_pop_create")
+        self._h = h
+        M = (_i64 * 3)()
+        tot = _i64()
+        q = ctypes.c_int()
+        w1 = _dbl()
+        sr = _dbl()
+        nb = _i64()
+        _check(lib().ace_pop_info(h, M, ctypes.byref(tot), ctypes.byref(q), ctypes.byref(w1),
+                                  ctypes.byref(sr), ctypes.byref(nb)), "ace_pop_info")
+        self.d = int(d)
+        self.shape = tuple(int(M[j]) for j in range(self.d))
+        self.total = int(tot.value)
+        self.q = int(q.value)
+        self.omega1 = float(w1.value)
+        self.s = float(sr.value)
+        self.device_bytes = int(nb.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ace_pop_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        _check(lib().ace_pop_set_stream(self._h, _vp(stream)), "ace_pop_set_stream")
+
+    def use_torch_stream(self):
+        self.set_stream(current_stream())
+
+    def set_kernel(self, kernel):
+        _check(lib().ace_pop_set_kernel(self._h, int(kernel)), "ace_pop_set_kernel")
+
+    def set_phi0(self, phi0):
+        if _is_device(phi0):
+            rc = lib().ace_pop_set_phi0(self._h, _dev(phi0), ACE_DEVICE)
+        else:
+            a, p = _host(phi0)
+            if a.size != self.total:
+                raise ValueError("phi0 has the wrong size")
+            rc = lib().ace_pop_set_phi0(self._h, p, ACE_HOST)
+        return _check(rc, "ace_pop_set_phi0")
+
+    def set_populations(self, f):
+        if _is_device(f):
+            return _check(lib().ace_pop_set_populations(self._h, _dev(f), ACE_DEVICE),
+                          "ace_pop_set_populations")
+        a, p = _host(f)
+        if a.size != self.q * self.total:
+            raise ValueError("populations have the wrong size")
+        return _check(lib().ace_pop_set_populations(self._h, p, ACE_HOST), "ace_pop_set_populations")
+
+    def get_populations(self, out=None):
+        if out is not None and _is_device(out):
+            _check(lib().ace_pop_get_populations(self._h, _dev(out), ACE_DEVICE),
+                   "ace_pop_get_populations")
+            return out
+        a = np.empty((self.q,) + self.shape)
+        _check(lib().ace_pop_get_populations(self._h, a.ctypes.data, ACE_HOST), "ace_pop_get_populations")
+        return a
+
+    def step(self, nsteps):
+        return _check(lib().ace_pop_step(self._h, int(nsteps)), "ace_pop_step")
+
+    def get_phi(self, out=None):
+        if out is not None and _is_device(out):
+            _check(lib().ace_pop_get_phi(self._h, _dev(out), ACE_DEVICE), "ace_pop_get_phi")
+            return out
+        a = np.empty(self.shape)
+        _check(lib().ace_pop_get_phi(self._h, a.ctypes.data, ACE_HOST), "ace_pop_get_phi")
+        return a
+
+    @property
+    def step_count(self):
+        return int(lib().ace_pop_step_count(self._h))
