@@ -279,6 +279,180 @@ __global__ __launch_bounds__(PNT) void k_pop_tiled(Shape s, PopCoef c, const dou
     }
 }
 
+// ---- update from phi (the split form) ------------------------------------
+// Reads phi (written by k_pop_moment) and writes the new populations.  A
+// workgroup of 512 threads owns a 16 x 64 output tile aligned to whole cache
+// lines (each wavefront stores 64 consecutive doubles of every population
+// array); phi of the tile plus its one-node ring sits in LDS (18 x 66), the
+// ring (160 values) loaded by threads 0..159 with one extra load each (the
+// other threads load their own node again, so every load is unconditional).
+// In 3D the workgroup marches along axis 0 with phi of planes z-1, z, z+1
+// of its own nodes in registers.
+constexpr int UX = 64;
+constexpr int UTR = 8;
+constexpr int URYT = 2;
+constexpr int UOY = UTR * URYT;  // 16
+constexpr int ULW = UX + 2;      // 66
+constexpr int ULH = UOY + 2;     // 18
+constexpr int ULP = ULW * ULH;
+constexpr int UNT = UX * UTR;    // 512
+constexpr int URING = 2 * UX + 2 * UOY;  // 160
+
+template <int D, int BC, int NIT>
+__global__ __launch_bounds__(UNT) void k_pop_update(Shape s, PopCoef c, const double *__restrict__ phi,
+                                                    double *__restrict__ fout, int tiles_x, int tiles_y,
+                                                    int zchunk)
+{
+    constexpr int Q = 2 * D + 1;
+    __shared__ double L[2 * ULP];
+    const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t ntile = (int64_t)tiles_x * tiles_y;
+    const int tile = (int)(t % ntile);
+    const int64_t chunk = t / ntile;
+    const int64_t x0 = (int64_t)(tile % tiles_x) * UX, y0 = (int64_t)(tile / tiles_x) * UOY;
+    const int lx = threadIdx.x & (UX - 1);
+    const int tr = threadIdx.x / UX;
+    const int64_t PS = s.M1 * s.M2;
+
+    // own nodes
+    int64_t off[URYT], oidx[URYT];
+    bool zr[URYT], ok[URYT];
+    const int64_t xg = x0 + lx;
+    bool zx = false;
+    const int64_t mx = pmap<BC>(xg, s.M2, zx);
+#pragma unroll
+    for (int r = 0; r < URYT; ++r) {
+        const int64_t yg = y0 + tr * URYT + r;
+        bool zy = false;
+        const int64_t my = pmap<BC>(yg, s.M1, zy);
+        off[r] = my * s.M2 + mx;
+        zr[r] = zx || zy;
+        ok[r] = xg < s.M2 && yg < s.M1;
+        oidx[r] = ok[r] ? yg * s.M2 + xg : 0;
+    }
+    // ring slot of this thread (threads >= URING reload their first node)
+    const int h = threadIdx.x;
+    int hslot = -1;
+    int64_t hoff = off[0];
+    bool hz = zr[0];
+    if (h < URING) {
+        int64_t hy, hx;
+        int ly, lxx;
+        if (h < UX) {  // row above
+            hy = y0 - 1; hx = x0 + h; ly = 0; lxx = 1 + h;
+        } else if (h < 2 * UX) {  // row below
+            hy = y0 + UOY; hx = x0 + (h - UX); ly = ULH - 1; lxx = 1 + (h - UX);
+        } else if (h < 2 * UX + UOY) {  // column left
+            hy = y0 + (h - 2 * UX); hx = x0 - 1; ly = 1 + (h - 2 * UX); lxx = 0;
+        } else {  // column right
+            hy = y0 + (h - 2 * UX - UOY); hx = x0 + UX; ly = 1 + (h - 2 * UX - UOY); lxx = ULW - 1;
+        }
+        bool z1 = false, z2 = false;
+        const int64_t my = pmap<BC>(hy, s.M1, z1);
+        const int64_t mxx = pmap<BC>(hx, s.M2, z2);
+        hoff = my * s.M2 + mxx;
+        hz = z1 || z2;
+        hslot = ly * ULW + lxx;
+    }
+
+    double own_raw[URYT], ring_raw;
+    bool zown = false, zring = false;
+    auto issue_own = [&](int64_t zz) {
+        zown = false;
+        const int64_t base = pmap<BC>(zz, s.M0, zown) * PS;
+#pragma unroll
+        for (int r = 0; r < URYT; ++r) own_raw[r] = phi[base + off[r]];
+    };
+    auto issue_ring = [&](int64_t zz) {
+        zring = false;
+        const int64_t base = pmap<BC>(zz, s.M0, zring) * PS;
+        ring_raw = phi[base + hoff];
+    };
+    auto own_val = [&](int r) { return (zown || zr[r]) ? 0.0 : own_raw[r]; };
+    auto stage = [&](double *Lb, const double (&pc)[URYT]) {
+#pragma unroll
+        for (int r = 0; r < URYT; ++r) Lb[(1 + tr * URYT + r) * ULW + 1 + lx] = pc[r];
+        if (hslot >= 0) Lb[hslot] = (zring || hz) ? 0.0 : ring_raw;
+    };
+    double outv[URYT][Q];
+    auto update_plane = [&](const double *Lc, const double (&pm)[URYT], const double (&pc)[URYT],
+                            const double (&pp)[URYT]) {
+#pragma unroll
+        for (int r = 0; r < URYT; ++r) {
+            if (!ok[r]) continue;
+            const int ly = 1 + tr * URYT + r, lxx = 1 + lx;
+            const double p = pc[r];
+            const double xm = Lc[ly * ULW + lxx - 1], xp = Lc[ly * ULW + lxx + 1];
+            const double ym = (r == 0) ? Lc[(ly - 1) * ULW + lxx] : pc[0];
+            const double yp = (r == URYT - 1) ? Lc[(ly + 1) * ULW + lxx] : pc[1];
+            if constexpr (D == 3) {
+                const double lo[3] = {pm[r], ym, xm}, hi[3] = {pp[r], yp, xp};
+                pop_update<3, NIT>(p, lo, hi, c, outv[r]);
+            } else {
+                const double lo[2] = {ym, xm}, hi[2] = {yp, xp};
+                pop_update<2, NIT>(p, lo, hi, c, outv[r]);
+            }
+        }
+    };
+    auto store_plane = [&](int64_t z) {
+#pragma unroll
+        for (int r = 0; r < URYT; ++r) {
+            if (!ok[r]) continue;
+            const int64_t o = z * PS + oidx[r];
+#pragma unroll
+            for (int k = 0; k < Q; ++k) fout[k * c.ps + o] = outv[r][k];
+        }
+    };
+
+    if constexpr (D == 2) {
+        double pc[URYT];
+        issue_own(0);
+        issue_ring(0);
+#pragma unroll
+        for (int r = 0; r < URYT; ++r) pc[r] = own_val(r);
+        stage(L, pc);
+        __syncthreads();
+        update_plane(L, pc, pc, pc);
+        store_plane(0);
+    } else {
+        const int64_t z0 = chunk * zchunk;
+        const int64_t z1 = std::min<int64_t>(z0 + zchunk, s.M0);
+        double pm[URYT], pc[URYT], pp[URYT];
+        issue_own(z0 - 1);
+#pragma unroll
+        for (int r = 0; r < URYT; ++r) pm[r] = own_val(r);
+        issue_own(z0);
+#pragma unroll
+        for (int r = 0; r < URYT; ++r) pc[r] = own_val(r);
+        issue_ring(z0);
+        stage(L, pc);
+        issue_own(z0 + 1);
+#pragma unroll
+        for (int r = 0; r < URYT; ++r) pp[r] = own_val(r);
+        int b = 0;
+        __syncthreads();
+        for (int64_t z = z0; z < z1; ++z) {
+            // own nodes of plane z+2 and the ring of plane z+1 (past the
+            // chunk the loads repeat a valid plane, unused)
+            issue_own(z + 2 < z1 + 1 ? z + 2 : z1);
+            issue_ring(z + 1 < z1 ? z + 1 : z1 - 1);
+            update_plane(L + b * ULP, pm, pc, pp);
+            // vmcnt(0) before this plane's stores (see k_pop_tiled)
+            __builtin_amdgcn_s_waitcnt(VMCNT0);
+            store_plane(z);
+            b ^= 1;
+#pragma unroll
+            for (int r = 0; r < URYT; ++r) {
+                pm[r] = pc[r];
+                pc[r] = pp[r];
+                pp[r] = own_val(r);
+            }
+            stage(L + b * ULP, pc);
+            __syncthreads();
+        }
+    }
+}
+
 __global__ void k_pop_moment(int q, int64_t ps, int64_t n, const double *__restrict__ f,
                              double *__restrict__ phi)
 {
@@ -324,8 +498,11 @@ hipError_t launch_pop_t(const Shape &s, const PopCoef &c, const double *fin, dou
         } else {
             hipLaunchKernelGGL(k_pop_moment, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, 2 * D + 1,
                                c.ps, n, fin, phi);
-            hipLaunchKernelGGL((k_pop_tiled<D, BC, NIT, false>), dim3((unsigned)nblk), dim3(PNT), 0, st, s,
-                               c, phi, fout, tiles_x, tiles_y, POP_ZCHUNK);
+            const int utx = (int)((s.M2 + UX - 1) / UX);
+            const int uty = (int)((s.M1 + UOY - 1) / UOY);
+            const int64_t ublk = (int64_t)utx * uty * chunks;
+            hipLaunchKernelGGL((k_pop_update<D, BC, NIT>), dim3((unsigned)ublk), dim3(UNT), 0, st, s, c, phi,
+                               fout, utx, uty, POP_ZCHUNK);
         }
     }
     return hipGetLastError();
