@@ -444,8 +444,8 @@ void load_tuning(ace_solver *s)
                    &zc, &k2, &ms) != 9)
             continue;
         if (d == s->p.d && bc == s->p.bc && m0 == s->p.M[0] && m1 == s->p.M[1] && m2 == s->p.M[2] &&
-            k >= ACE_KERNEL_DIRECT && k <= ACE_KERNEL_TBLOCK && (zc == 0 || zc >= TBLOCK_MIN_ZCHUNK) && k2 >= 1 &&
-            k2 <= tblock2d_max_depth()) {
+            k >= ACE_KERNEL_DIRECT && k <= ACE_KERNEL_TBLOCK &&
+            (zc == 0 || zc >= TBLOCK_MIN_ZCHUNK) && k2 >= 1 && k2 <= tblock2d_max_depth()) {
             s->tuned_kernel = k;
             s->zchunk = zc;
             s->depth2 = k2;

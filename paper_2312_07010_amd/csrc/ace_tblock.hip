@@ -77,13 +77,12 @@ __device__ __forceinline__ double load_at2(const double *__restrict__ in, int64_
     return (base < 0 || off < 0) ? 0.0 : in[base + off];
 }
 
-template <int BC, bool MON, int NIT>
 // amdgpu_waves_per_eu(4) caps the kernel at 128 VGPRs, so two 512-thread
 // workgroups (LDS 72 KB each) share a CU.
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_tblock3d(Shape s, StepCoef c, const double *__restrict__ in,
-                                                 double *__restrict__ out,
-                                                 double *__restrict__ partials, int tiles_x,
-                                                 int tiles_y, int zchunk)
+template <int BC, bool MON, int NIT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_tblock3d(
+    Shape s, StepCoef c, const double *__restrict__ in, double *__restrict__ out,
+    double *__restrict__ partials, int tiles_x, int tiles_y, int zchunk)
 {
     __shared__ double L0[2 * LP];
     __shared__ double L1[2 * LP];

@@ -19,6 +19,8 @@
 //   lambda_j = (1 - h (3 phi_j^2 - 1)) mu + kappa Lambda mu,
 //   g += < mu, Lambda phi_j > over the tile,
 // reading the stored states phi_j, phi_{j+1} of each level into LDS.
+#include <type_traits>
+
 #include "ace_device.h"
 
 namespace ace {
@@ -92,7 +94,9 @@ __device__ __forceinline__ void yoffs(const Shape &s, const Geo &g, int ry, int 
     (void)tx;
 }
 
-template <int BC, bool MON, bool LEVELS>
+// NIT > 0: the Newton count fixed at compile time (unrolled; identical
+// rounding to the runtime count, see cubic_root_n); 0: the runtime count.
+template <int BC, bool MON, bool LEVELS, int NIT>
 __global__ __launch_bounds__(BNT) void k_tblock2d(Shape s, StepCoef c, const double *__restrict__ in,
                                                   double *__restrict__ out,
                                                   double *__restrict__ partials, int K, int tiles_x,
@@ -149,7 +153,7 @@ __global__ __launch_bounds__(BNT) void k_tblock2d(Shape s, StepCoef c, const dou
             const int o = (ry + 1) * BLW + tx + 1;
             const double p = src[o];
             const double nsum = (src[o + ym] + src[o + yp]) + (src[o + g.xm] + src[o + g.xp]);
-            const double v = update<2>(p, nsum, c);
+            const double v = update_n<2, NIT>(p, nsum, c);
             dst[o] = v;
             if (LEVELS || k == K) {
                 const int64_t yg = g.y0r + ry;
@@ -279,6 +283,44 @@ int64_t tblock2d_blocks(const Shape &s, int K)
     return n;
 }
 
+namespace {
+
+template <int BC, int NIT>
+hipError_t launch_t2(const Shape &s, const StepCoef &c, const double *in, double *out, double *partials,
+                     int K, int tiles_x, int ntiles, int64_t level_stride, bool levels, hipStream_t st)
+{
+    if (partials)
+        hipLaunchKernelGGL((k_tblock2d<BC, true, false, NIT>), dim3(ntiles), dim3(BNT), 0, st, s, c, in,
+                           out, partials, K, tiles_x, level_stride);
+    else if (levels)
+        hipLaunchKernelGGL((k_tblock2d<BC, false, true, NIT>), dim3(ntiles), dim3(BNT), 0, st, s, c, in,
+                           out, partials, K, tiles_x, level_stride);
+    else
+        hipLaunchKernelGGL((k_tblock2d<BC, false, false, NIT>), dim3(ntiles), dim3(BNT), 0, st, s, c, in,
+                           out, partials, K, tiles_x, level_stride);
+    return hipGetLastError();
+}
+
+template <int BC>
+hipError_t launch_t2_nit(const Shape &s, const StepCoef &c, const double *in, double *out,
+                         double *partials, int K, int tiles_x, int ntiles, int64_t level_stride,
+                         bool levels, hipStream_t st)
+{
+    const int nit = c.fex ? 0 : c.nit;
+    auto go = [&](auto tag) {
+        return launch_t2<BC, decltype(tag)::value>(s, c, in, out, partials, K, tiles_x, ntiles, level_stride,
+                                                   levels, st);
+    };
+    switch (nit) {
+    case 1: return go(std::integral_constant<int, 1>());
+    case 2: return go(std::integral_constant<int, 2>());
+    case 3: return go(std::integral_constant<int, 3>());
+    default: return go(std::integral_constant<int, 0>());
+    }
+}
+
+}  // namespace
+
 hipError_t launch_step_tblock2d(const Shape &s, const StepCoef &c, const double *in, double *out,
                                 double *partials, int64_t *nparts, int K, int64_t level_stride,
                                 hipStream_t st)
@@ -288,22 +330,16 @@ hipError_t launch_step_tblock2d(const Shape &s, const StepCoef &c, const double 
     tiles2d(s, K, tiles_x, ntiles);
     if (nparts) *nparts = ntiles;
     const bool levels = level_stride > 0;
-#define ACE_T2(BB)                                                                               \
-    if (s.bc == BB) {                                                                            \
-        if (partials)                                                                            \
-            hipLaunchKernelGGL((k_tblock2d<BB, true, false>), dim3(ntiles), dim3(BNT), 0, st, s,  \
-                               c, in, out, partials, K, tiles_x, level_stride);                  \
-        else if (levels)                                                                         \
-            hipLaunchKernelGGL((k_tblock2d<BB, false, true>), dim3(ntiles), dim3(BNT), 0, st, s,  \
-                               c, in, out, partials, K, tiles_x, level_stride);                  \
-        else                                                                                     \
-            hipLaunchKernelGGL((k_tblock2d<BB, false, false>), dim3(ntiles), dim3(BNT), 0, st,    \
-                               s, c, in, out, partials, K, tiles_x, level_stride);               \
-        return hipGetLastError();                                                                \
+    switch (s.bc) {
+    case BC_HN:
+        return launch_t2_nit<BC_HN>(s, c, in, out, partials, K, tiles_x, ntiles, level_stride, levels, st);
+    case BC_HD:
+        return launch_t2_nit<BC_HD>(s, c, in, out, partials, K, tiles_x, ntiles, level_stride, levels, st);
+    case BC_P:
+        return launch_t2_nit<BC_P>(s, c, in, out, partials, K, tiles_x, ntiles, level_stride, levels, st);
+    default:
+        return hipErrorInvalidValue;
     }
-    ACE_T2(BC_HN) ACE_T2(BC_HD) ACE_T2(BC_P)
-#undef ACE_T2
-    return hipErrorInvalidValue;
 }
 
 hipError_t launch_adjoint_tblock2d(const Shape &s, const StepCoef &c, const double *lam_in,
