@@ -36,11 +36,10 @@ def _sha(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(kname, plane_chunk):
-    """HBM bytes per launch of the step kernel from the committed rocprofv3
-    FETCH_SIZE/WRITE_SIZE runs (scaled by a copy of known size), if they were
-    taken on the current source of that kernel and of the device header and
-    at the same launch shape (planes per workgroup); else None."""
+def committed_counters(kname, plane_chunk):
+    """(figures for this launch shape, VALU peak) from the committed rocprofv3
+    summary of the kernel, if it was taken on the current source of the kernel
+    and of the device header; else None."""
     path = os.path.join(ROOT, "profiles", f"{kname}_p512_traffic.json")
     try:
         with open(path) as f:
@@ -50,9 +49,17 @@ def measured_traffic(kname, plane_chunk):
         return None
     if t.get("kernel_src_sha") != src:
         return None
-    shapes = t.get("by_plane_chunk", {})
     key = str(plane_chunk) if kname == "k_tblock3d" else "any"
-    return shapes.get(key, {}).get("bytes_per_launch")
+    return t.get("by_plane_chunk", {}).get(key), t.get("valu_peak_lane_instr_per_s")
+
+
+def measured_traffic(kname, plane_chunk):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE runs (scaled by a copy of known size), if they were
+    taken on the current source of that kernel and of the device header and
+    at the same launch shape (planes per workgroup); else None."""
+    cc = committed_counters(kname, plane_chunk)
+    return cc[0].get("bytes_per_launch") if cc and cc[0] else None
 
 
 def cpu_baseline(w, phi0_full, min_seconds=10.0):
@@ -371,6 +378,11 @@ def main():
             "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_launch_s * 1e6}
     if w.d == 3:
         roof["plane_chunk"] = r["plane_chunk"]
+    cc = committed_counters(r["kernel"], r["plane_chunk"])
+    if cc and cc[0] and cc[1] and "sq_per_launch" in cc[0]:
+        # VALU issue time of one launch (committed SQ_INSTS_VALU x 64 lanes at
+        # the peak lane-instruction rate) over the launch time measured here
+        roof["valu_frac"] = cc[0]["sq_per_launch"]["SQ_INSTS_VALU"] * 64 / cc[1] / avg_launch_s
 
     out = {
         "metric": "FP64 grid-pt updates/s + % HBM roofline; adjoint cost ratio; batched vs looped",
