@@ -166,6 +166,7 @@ def batched_speedup(ace, torch):
         s.close()
     return {"speedup": t_loop / t_batch, "batched_s": t_batch, "looped_s": t_loop,
             "batched_updates_per_s": updates / t_batch,
+            "algorithmic_hbm_frac": BYTES_PER_UPDATE * updates / t_batch / HBM_PEAK,
             "resident_limit": tune["choice"]["resident_limit"]}
 
 
@@ -423,6 +424,19 @@ def main():
         out["fex_scheme"] = {"value": n * steps / fwall, "unit": "grid-pt updates/s",
                              "roofline_frac": bytes_per_launch / favg / HBM_PEAK,
                              "kernel": roof["kernel"]}
+        s.set_scheme(ace.ACE_SCHEME_RLB_MIE)
+        # the standalone reductions over the same field: the energy / max-norm
+        # monitor pass and the phase volume of the radius diagnostics (each
+        # reads the field once, 8 B per node; synchronous calls, host clock)
+        red = {}
+        for name, fn in (("energy_monitor", s.energy), ("phase_volume", s.phase_volume)):
+            fn()
+            t0 = time.perf_counter()
+            for _ in range(20):
+                fn()
+            t = (time.perf_counter() - t0) / 20
+            red[name] = {"ms": t * 1e3, "hbm_frac": 8.0 * n / t / HBM_PEAK}
+        out["reductions"] = red
     s.close()
     phi0 = r["phi0"]
     del r

@@ -283,11 +283,23 @@ int steps_per_launch_of(const ace_solver *s, int kernel)
 // steps_per_launch_of() with the temporal-blocking kernels.  If want_mon,
 // the monitor partials of the input field are left in s->partials, their
 // count in *nparts.  Returns the number of steps taken (or a negative error).
+// Partial triples a monitored launch of `kernel` writes (the launch that
+// launch_steps makes for `remaining` steps).
+int64_t partials_for(const ace_solver *s, int kernel, int64_t remaining)
+{
+    if (kernel == ACE_KERNEL_TBLOCK && s->p.d == 2)
+        return tblock2d_blocks(s->shape, (int)std::min<int64_t>(s->depth2, remaining));
+    if (kernel == ACE_KERNEL_TBLOCK && remaining >= 2) return tblock_partials_needed(s->shape, s->zchunk);
+    if (kernel == ACE_KERNEL_MARCH || kernel == ACE_KERNEL_TBLOCK) return march_partials_needed(s->shape);
+    return direct_partials_needed(s->shape);
+}
+
 int launch_steps(ace_solver *s, int kernel, int64_t remaining, bool want_mon, int64_t *nparts)
 {
     const double *in = s->buf[s->cur];
     double *out = s->buf[s->cur ^ 1];
     double *parts = want_mon ? s->partials : nullptr;
+    if (want_mon && 3 * partials_for(s, kernel, remaining) > s->partials_cap) return ACE_E_STATE;
     hipError_t e;
     int taken = 1;
     if (kernel == ACE_KERNEL_TBLOCK && s->p.d == 2) {
@@ -396,9 +408,9 @@ int alloc_fields(ace_solver *s)
         if (e != hipSuccess) return hip_status(e);
         s->buf[i] = s->own[i];
     }
-    const int64_t need = std::max<int64_t>(
-        std::max<int64_t>(monitor_partials_needed(s->shape), 1), 1) * 3;
-    int64_t need2 = need;
+    // one partial triple per workgroup of any monitored launch
+    int64_t need2 = 3 * std::max<int64_t>(
+        std::max<int64_t>(monitor_partials_needed(s->shape), direct_partials_needed(s->shape)), 1);
     if (march_supported(s->shape)) need2 = std::max<int64_t>(need2, 3 * march_partials_needed(s->shape));
     if (tblock_supported(s->shape))
         need2 = std::max<int64_t>(need2, 3 * tblock_partials_needed(s->shape, TBLOCK_MIN_ZCHUNK));
@@ -421,6 +433,7 @@ int read_triple(ace_solver *s, const double *dev, double *host3)
 int monitor_now(ace_solver *s, double *dev_out)
 {
     int64_t np = 0;
+    if (3 * monitor_partials_needed(s->shape) > s->partials_cap) return ACE_E_STATE;
     ACE_HIP(launch_monitor(s->shape, s->buf[s->cur], s->partials, &np, s->stream));
     ACE_HIP(launch_reduce(s->partials, np, dev_out, s->stream));
     return ACE_OK;

@@ -38,6 +38,8 @@ hipError_t launch_step_direct(const Shape &s, const StepCoef &c, const double *i
                               double *out, double *partials, int64_t *nparts,
                               hipStream_t st);
 
+int64_t direct_partials_needed(const Shape &s);  // blocks of launch_step_direct
+
 // Monitor partials of a field without stepping.
 hipError_t launch_monitor(const Shape &s, const double *in, double *partials,
                           int64_t *nparts, hipStream_t st);

@@ -17,10 +17,16 @@
 // f_k(t + dt) = R_k - w_k h f(theta).
 //
 // Populations are stored one array per k (k = 0 at rest, 1..d along +axis,
-// d+1..2d along -axis, axis 0 the slowest), each `ps` doubles apart (ps is
-// the node count rounded up to 32, so every array starts on 256 bytes).
-// The tiled kernel reads each node's 2d+1 populations once and writes them
-// once: 16 (2d+1) bytes of HBM per node update, against 16 for the FD step.
+// d+1..2d along -axis, axis 0 the slowest), each `ps` doubles apart (the
+// node count rounded up to 32 plus a 1280-byte stagger, so every array
+// starts on 256 bytes and the arrays do not start on the same HBM channel).
+// Any step reads each node's 2d+1 populations and writes them: at least
+// 16 (2d+1) bytes of HBM per node update, against 16 for the FD step.
+// Three kernels compute the same result bit for bit: one thread per node
+// (k_pop_direct), a fused tiled march (k_pop_tiled), and the split form, a
+// streaming moment pass (k_pop_moment) followed by an update from phi on
+// cache-line-aligned tiles (k_pop_update), 16 (2d+1) + 16 bytes per node
+// update with aligned streams; the split form is the default for d >= 2.
 #include <math.h>
 #include <string.h>
 
@@ -142,15 +148,12 @@ constexpr int PLP = PRH * PX;
 // 15:14 zero, expcnt 6:4 and lgkmcnt 11:8 at their maxima)
 constexpr int VMCNT0 = 0x0F70;
 
-// FUSED: `fin` holds the populations and phi is summed here; otherwise
-// `fin` is phi itself (written by k_pop_moment).
-template <int D, int BC, int NIT, bool FUSED>
+template <int D, int BC, int NIT>
 __global__ __launch_bounds__(PNT) void k_pop_tiled(Shape s, PopCoef c, const double *__restrict__ fin,
                                                    double *__restrict__ fout, int tiles_x, int tiles_y,
                                                    int zchunk)
 {
     constexpr int Q = 2 * D + 1;
-    constexpr int QIN = FUSED ? Q : 1;
     __shared__ double L[2 * PLP];
     const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t ntile = (int64_t)tiles_x * tiles_y;
@@ -179,7 +182,7 @@ __global__ __launch_bounds__(PNT) void k_pop_tiled(Shape s, PopCoef c, const dou
         oidx[r] = ok[r] ? yg * s.M2 + xg : 0;
     }
 
-    double raw[QIN][PRYT];
+    double raw[Q][PRYT];
     bool zplane = false;
     auto issue = [&](int64_t zz) {
         zplane = false;
@@ -187,14 +190,14 @@ __global__ __launch_bounds__(PNT) void k_pop_tiled(Shape s, PopCoef c, const dou
 #pragma unroll
         for (int r = 0; r < PRYT; ++r)
 #pragma unroll
-            for (int k = 0; k < QIN; ++k) raw[k][r] = fin[k * c.ps + base + off[r]];
+            for (int k = 0; k < Q; ++k) raw[k][r] = fin[k * c.ps + base + off[r]];
     };
     auto consume = [&](double (&ph)[PRYT]) {
 #pragma unroll
         for (int r = 0; r < PRYT; ++r) {
             double v = raw[0][r];
 #pragma unroll
-            for (int k = 1; k < QIN; ++k) v += raw[k][r];
+            for (int k = 1; k < Q; ++k) v += raw[k][r];
             ph[r] = (zplane || zr[r]) ? 0.0 : v;
         }
     };
@@ -493,8 +496,8 @@ hipError_t launch_pop_t(const Shape &s, const PopCoef &c, const double *fin, dou
         const int64_t chunks = (D == 3) ? (s.M0 + POP_ZCHUNK - 1) / POP_ZCHUNK : 1;
         const int64_t nblk = (int64_t)tiles_x * tiles_y * chunks;
         if (mode == 1) {
-            hipLaunchKernelGGL((k_pop_tiled<D, BC, NIT, true>), dim3((unsigned)nblk), dim3(PNT), 0, st, s,
-                               c, fin, fout, tiles_x, tiles_y, POP_ZCHUNK);
+            hipLaunchKernelGGL((k_pop_tiled<D, BC, NIT>), dim3((unsigned)nblk), dim3(PNT), 0, st, s, c,
+                               fin, fout, tiles_x, tiles_y, POP_ZCHUNK);
         } else {
             hipLaunchKernelGGL(k_pop_moment, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, 2 * D + 1,
                                c.ps, n, fin, phi);

@@ -286,25 +286,154 @@ hipError_t launch_step_direct(const Shape &s, const StepCoef &c, const double *i
     return dispatch_direct<false>(s, c, in, out, nullptr, grid, block, st);
 }
 
-int64_t monitor_partials_needed(const Shape &s)
+// ---------------------------------------------------------------------------
+// Monitor partials of a 2D/3D field on tiles marching along axis 0: a
+// 256-thread workgroup owns 16 rows x 64 columns of the two fastest axes and
+// a chunk of MZ planes, so the grid (and the partials the one-block
+// reduction then reads) is small.  The per-node terms are those of k_monitor
+// in the same order; the +x and +y neighbours come from loads at wrapped or
+// clamped coordinates (always valid, so every load is unconditional) and +z
+// from the next plane, which the march loads anyway.
+// ---------------------------------------------------------------------------
+constexpr int MTX = 64;
+constexpr int MTR = 4;
+constexpr int MRY = 4;
+constexpr int MTY = MTR * MRY;  // 16 rows per tile
+constexpr int MNT = MTX * MTR;  // 256 threads
+constexpr int MZ = 64;
+
+template <int D, int BC>
+__global__ __launch_bounds__(MNT) void k_monitor_tiles(Shape s, const double *__restrict__ in,
+                                                      double *__restrict__ partials, int tiles_x,
+                                                      int tiles_y)
+{
+    __shared__ double lds[3 * (MNT / 64)];
+    const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t ntile = (int64_t)tiles_x * tiles_y;
+    const int tile = (int)(t % ntile);
+    const int64_t chunk = t / ntile;
+    const int lane = threadIdx.x & (MTX - 1);
+    const int tr = threadIdx.x / MTX;
+    const int64_t x = (int64_t)(tile % tiles_x) * MTX + lane;
+    const int64_t ybase = (int64_t)(tile / tiles_x) * MTY + tr * MRY;
+    const int64_t PS = s.M1 * s.M2;
+    const bool xin = x < s.M2;
+    const int64_t cx = xin ? x : s.M2 - 1;
+    const bool xlast = x + 1 >= s.M2;
+    const int64_t xn = xlast ? (BC == BC_P ? 0 : cx) : x + 1;  // wrap index for periodic
+    int64_t row[MRY], rown[MRY];
+    bool yin[MRY], ylast[MRY];
+#pragma unroll
+    for (int r = 0; r < MRY; ++r) {
+        const int64_t y = ybase + r;
+        yin[r] = y < s.M1;
+        const int64_t cy = yin[r] ? y : s.M1 - 1;
+        ylast[r] = y + 1 >= s.M1;
+        row[r] = cy * s.M2;
+        rown[r] = (ylast[r] ? (BC == BC_P ? 0 : cy) : y + 1) * s.M2;
+    }
+    const int64_t z0 = chunk * MZ;
+    const int64_t z1 = (z0 + MZ < s.M0) ? z0 + MZ : s.M0;
+    MonAcc m;
+    mon_zero(m);
+    double cur[MRY];
+#pragma unroll
+    for (int r = 0; r < MRY; ++r) cur[r] = in[z0 * PS + row[r] + cx];
+    for (int64_t z = z0; z < z1; ++z) {
+        const bool zlast = z + 1 >= s.M0;
+        const int64_t zn = zlast ? (BC == BC_P ? 0 : z) : z + 1;
+        double nxt[MRY], vx[MRY], vy[MRY];
+#pragma unroll
+        for (int r = 0; r < MRY; ++r) {
+            nxt[r] = in[zn * PS + row[r] + cx];
+            vx[r] = in[z * PS + row[r] + xn];
+            vy[r] = in[z * PS + rown[r] + cx];
+        }
+#pragma unroll
+        for (int r = 0; r < MRY; ++r) {
+            if (!(xin && yin[r])) continue;
+            const double p = cur[r];
+            double grad = 0.0;
+            if (D == 3) {
+                const double hi = zlast ? outside<BC>(p, nxt[r]) : nxt[r];
+                const double dh = hi - p;
+                grad = fma(dh, dh, grad);
+                if (BC == BC_HD && z == 0) grad = fma(p, p, grad);
+            }
+            {
+                const double hi = ylast[r] ? outside<BC>(p, vy[r]) : vy[r];
+                const double dh = hi - p;
+                grad = fma(dh, dh, grad);
+                if (BC == BC_HD && ybase + r == 0) grad = fma(p, p, grad);
+            }
+            {
+                const double hi = xlast ? outside<BC>(p, vx[r]) : vx[r];
+                const double dh = hi - p;
+                grad = fma(dh, dh, grad);
+                if (BC == BC_HD && x == 0) grad = fma(p, p, grad);
+            }
+            m.bulk += bulk_term(p);
+            m.grad += grad;
+            m.mx = nan_max(m.mx, fabs(p));
+        }
+#pragma unroll
+        for (int r = 0; r < MRY; ++r) cur[r] = nxt[r];
+    }
+    block_reduce_store(m, lds, partials + 3 * blockIdx.x);
+}
+
+void monitor_tiles_grid(const Shape &s, int &tiles_x, int &tiles_y, int64_t &nblk)
+{
+    tiles_x = (int)((s.M2 + MTX - 1) / MTX);
+    tiles_y = (int)((s.M1 + MTY - 1) / MTY);
+    nblk = (int64_t)tiles_x * tiles_y * ((s.M0 + MZ - 1) / MZ);
+}
+
+int64_t direct_partials_needed(const Shape &s)
 {
     dim3 grid, block;
     direct_grid(s, grid, block);
     return (int64_t)grid.x * grid.y * grid.z;
 }
 
+int64_t monitor_partials_needed(const Shape &s)
+{
+    if (s.d == 1) {
+        dim3 grid, block;
+        direct_grid(s, grid, block);
+        return (int64_t)grid.x * grid.y * grid.z;
+    }
+    int tx, ty;
+    int64_t nblk;
+    monitor_tiles_grid(s, tx, ty, nblk);
+    return nblk;
+}
+
 hipError_t launch_monitor(const Shape &s, const double *in, double *partials, int64_t *nparts,
                           hipStream_t st)
 {
-    dim3 grid, block;
-    direct_grid(s, grid, block);
-    if (nparts) *nparts = (int64_t)grid.x * grid.y * grid.z;
-#define ACE_MON(DD, BB)                                                                  \
-    if (s.d == DD && s.bc == BB) {                                                       \
-        hipLaunchKernelGGL((k_monitor<DD, BB>), grid, block, 0, st, s, in, partials);    \
-        return hipGetLastError();                                                        \
+    if (s.d == 1) {
+        dim3 grid, block;
+        direct_grid(s, grid, block);
+        if (nparts) *nparts = (int64_t)grid.x * grid.y * grid.z;
+        switch (s.bc) {
+        case BC_HN: hipLaunchKernelGGL((k_monitor<1, BC_HN>), grid, block, 0, st, s, in, partials); break;
+        case BC_HD: hipLaunchKernelGGL((k_monitor<1, BC_HD>), grid, block, 0, st, s, in, partials); break;
+        case BC_P: hipLaunchKernelGGL((k_monitor<1, BC_P>), grid, block, 0, st, s, in, partials); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
     }
-    ACE_MON(1, BC_HN) ACE_MON(1, BC_HD) ACE_MON(1, BC_P)
+    int tx, ty;
+    int64_t nblk;
+    monitor_tiles_grid(s, tx, ty, nblk);
+    if (nparts) *nparts = nblk;
+#define ACE_MON(DD, BB)                                                                              \
+    if (s.d == DD && s.bc == BB) {                                                                   \
+        hipLaunchKernelGGL((k_monitor_tiles<DD, BB>), dim3((unsigned)nblk), dim3(MNT), 0, st, s, in, \
+                           partials, tx, ty);                                                        \
+        return hipGetLastError();                                                                    \
+    }
     ACE_MON(2, BC_HN) ACE_MON(2, BC_HD) ACE_MON(2, BC_P)
     ACE_MON(3, BC_HN) ACE_MON(3, BC_HD) ACE_MON(3, BC_P)
 #undef ACE_MON
