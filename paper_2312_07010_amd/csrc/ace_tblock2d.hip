@@ -1,8 +1,8 @@
 // 2D temporal blocking: K steps of the scheme (or K transposed steps) per
 // launch on LDS-resident regions.
 //
-// A workgroup (256 threads: one wavefront per region row, four thread rows,
-// region row r handled by thread row r % 4) loads the 32 x 64 region around a
+// A workgroup (512 threads: one wavefront per region row, eight thread rows,
+// region row r handled by thread row r % 8) loads the 32 x 64 region around a
 // (32 - 2K) x (64 - 2K) tile, with a ring of K nodes, into a padded LDS
 // plane and advances it K times between two LDS buffers (one barrier per
 // step).  After step k only rows [k, 32 - k) are still needed, so wavefronts
@@ -28,10 +28,10 @@ namespace ace {
 namespace {
 
 constexpr int BX = 64;           // region width (one wavefront)
-constexpr int BTR = 4;           // thread rows
+constexpr int BTR = 8;           // thread rows
 constexpr int BH = 32;           // region height
 constexpr int BRT = BH / BTR;    // rows per thread
-constexpr int BNT = BX * BTR;    // 256 threads
+constexpr int BNT = BX * BTR;    // 512 threads
 constexpr int BLW = BX + 2;      // padded LDS row
 constexpr int BLH = BH + 2;
 constexpr int BLP = BLW * BLH;
@@ -260,7 +260,11 @@ __global__ __launch_bounds__(BNT) void k_adjoint_tb2d(Shape s, StepCoef c,
     gsum = wave_sum(gsum);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = gsum;
     __syncthreads();
-    if (threadIdx.x == 0) gpart[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (threadIdx.x == 0) {
+        double t = red[0];
+        for (int w = 1; w < BNT / 64; ++w) t += red[w];
+        gpart[blockIdx.x] = t;
+    }
 }
 
 void tiles2d(const Shape &s, int K, int &tiles_x, int &ntiles)
