@@ -140,13 +140,15 @@ hipError_t dispatch_direct(const Shape &s, const StepCoef &c, const double *in, 
 constexpr int kResThreads = 1024;
 constexpr int kResNodes = (int)((RESIDENT_MAX + kResThreads - 1) / kResThreads);
 
-template <int D, int BC>
+// The field alternates between two LDS buffers (one barrier per step); NIT
+// as in update_n (0: the runtime Newton count).
+template <int D, int BC, int NIT>
 __global__ __launch_bounds__(kResThreads) void k_resident(Shape s, StepCoef c,
                                                           double *__restrict__ field,
                                                           int64_t nsteps, int64_t every,
                                                           double *__restrict__ mon)
 {
-    __shared__ double f[RESIDENT_MAX + 1];
+    __shared__ double fb[2][RESIDENT_MAX + 1];
     __shared__ double red[3 * (kResThreads / 64)];
     const int total = (int)(s.M0 * s.M1 * s.M2);
     const int tid = threadIdx.x;
@@ -171,11 +173,16 @@ __global__ __launch_bounds__(kResThreads) void k_resident(Shape s, StepCoef c,
             nb_hi[k][a] = hi;
         }
     }
-    for (int j = tid; j < total; j += nt) f[j] = field[j];
-    if (tid == 0) f[total] = 0.0;
+    for (int j = tid; j < total; j += nt) fb[0][j] = field[j];
+    if (tid == 0) {
+        fb[0][total] = 0.0;
+        fb[1][total] = 0.0;
+    }
     __syncthreads();
     int64_t jm = 0;
+    int cb = 0;
     for (int64_t step = 0;; ++step) {
+        const double *f = fb[cb];
         if (every > 0 && step % every == 0) {
             MonAcc m;
             mon_zero(m);
@@ -201,28 +208,22 @@ __global__ __launch_bounds__(kResThreads) void k_resident(Shape s, StepCoef c,
             __syncthreads();
         }
         if (step == nsteps) break;
-        double nv[kResNodes];
+        double *fn = fb[cb ^ 1];
 #pragma unroll
         for (int k = 0; k < kResNodes; ++k) {
             const int j = tid + k * nt;
-            nv[k] = 0.0;
             if (j < total) {
                 const double p = f[j];
                 double nsum = 0.0;
 #pragma unroll
                 for (int a = 3 - D; a < 3; ++a) nsum += f[nb_lo[k][a]] + f[nb_hi[k][a]];
-                nv[k] = update<D>(p, nsum, c);
+                fn[j] = update_n<D, NIT>(p, nsum, c);
             }
         }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kResNodes; ++k) {
-            const int j = tid + k * nt;
-            if (j < total) f[j] = nv[k];
-        }
+        cb ^= 1;
         __syncthreads();
     }
-    for (int j = tid; j < total; j += nt) field[j] = f[j];
+    for (int j = tid; j < total; j += nt) field[j] = fb[cb][j];
 }
 
 __global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ partials, int64_t n,
@@ -472,16 +473,22 @@ hipError_t launch_resident(const Shape &s, const StepCoef &c, double *field, int
     if (threads > kResThreads) threads = kResThreads;
     // every node index tid + k * threads must fit in kResNodes slots
     if ((total + threads - 1) / threads > kResNodes) return hipErrorInvalidValue;
-#define ACE_RES(DD, BB)                                                                      \
-    if (s.d == DD && s.bc == BB) {                                                           \
-        hipLaunchKernelGGL((k_resident<DD, BB>), dim3(1), dim3(threads), 0, st, s, c, field, \
-                           nsteps, every, mon);                                              \
-        return hipGetLastError();                                                            \
+#define ACE_RES_N(DD, BB, NN)                                                                    \
+    hipLaunchKernelGGL((k_resident<DD, BB, NN>), dim3(1), dim3(threads), 0, st, s, c, field, nsteps, \
+                       every, mon);                                                              \
+    return hipGetLastError();
+#define ACE_RES(DD, BB)                                          \
+    if (s.d == DD && s.bc == BB) {                               \
+        if (!c.fex && c.nit == 1) { ACE_RES_N(DD, BB, 1) }       \
+        if (!c.fex && c.nit == 2) { ACE_RES_N(DD, BB, 2) }       \
+        if (!c.fex && c.nit == 3) { ACE_RES_N(DD, BB, 3) }       \
+        ACE_RES_N(DD, BB, 0)                                     \
     }
     ACE_RES(1, BC_HN) ACE_RES(1, BC_HD) ACE_RES(1, BC_P)
     ACE_RES(2, BC_HN) ACE_RES(2, BC_HD) ACE_RES(2, BC_P)
     ACE_RES(3, BC_HN) ACE_RES(3, BC_HD) ACE_RES(3, BC_P)
 #undef ACE_RES
+#undef ACE_RES_N
     return hipErrorInvalidValue;
 }
 
