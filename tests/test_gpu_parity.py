@@ -280,3 +280,23 @@ def test_3d_persistent_grid_fills_the_device(ace, orc):
     s.set_phi0(phi0)
     s.step(4)
     np.testing.assert_allclose(s.get_phi(), want, rtol=0, atol=1e-13)
+
+
+def test_plane_chunk_arguments(ace, orc):
+    s, p = _pair(ace, orc, 3, 20, 2)
+    for bad in (-1, 1, 7, 4097):
+        with pytest.raises(ace.AceError):
+            s.set_plane_chunk(bad)
+    for good in (0, 8, 4096):
+        s.set_plane_chunk(good)
+        assert s.get_plane_chunk() == good
+    s2, _ = _pair(ace, orc, 2, 20, 2)
+    with pytest.raises(ace.AceError):
+        s2.set_plane_chunk(32)
+    # a persistent grid on a field smaller than one workgroup's share
+    s.set_kernel(ace.ACE_KERNEL_TBLOCK)
+    s.set_plane_chunk(0)
+    phi0 = np.random.default_rng(2).uniform(-1, 1, p.shape)
+    s.set_phi0(phi0)
+    s.step(4)
+    np.testing.assert_allclose(s.get_phi(), p.run(phi0, 4)[0], rtol=0, atol=1e-14)

@@ -106,6 +106,12 @@ def test_edge_cases(ace, orc):
             ace.Pop(*_args(2, (10, 12), 0, 0.1), omega1=bad)
     with pytest.raises(ace.AceError):
         g.set_kernel(4)
+    bad = phi0.copy()
+    bad[2, 3] = np.inf
+    with pytest.raises(ace.AceError):
+        g.set_phi0(bad)
+    with pytest.raises(ValueError):
+        g.set_populations(np.zeros(7))
     g.close()
 
 
