@@ -276,12 +276,12 @@ int ace_pop_info(const ace_pop *p, int64_t M[3], int64_t *total, int *q, double 
 int ace_pop_set_stream(ace_pop *p, void *hip_stream);
 /* Kernel of ace_pop_step (every choice computes the same result bit for
  * bit): ACE_POP_DIRECT one thread per node, phi of the node and its
- * neighbours summed from their populations; ACE_POP_FUSED tiles marching
- * along axis 0 that sum phi of a region into LDS and write the new
- * populations of its interior (16 (2d+1) bytes per node update);
- * ACE_POP_SPLIT a streaming pass writing phi = sum_k f_k, then the tiled
- * update reading phi (16 (2d+1) + 16 bytes, aligned streams);
- * ACE_POP_AUTO: split for d >= 2, direct for d = 1. */
+ * neighbours summed from their populations; ACE_POP_FUSED cache-line-
+ * aligned tiles marching along axis 0 that sum phi of the tile and its ring
+ * into LDS and write the new populations (16 (2d+1) bytes per node update);
+ * ACE_POP_SPLIT a streaming pass writing phi = sum_k f_k, then the same
+ * tiled update reading phi (16 (2d+1) + 16 bytes);
+ * ACE_POP_AUTO: the fused form for d >= 2, direct for d = 1. */
 #define ACE_POP_AUTO 0
 #define ACE_POP_DIRECT 1
 #define ACE_POP_FUSED 2

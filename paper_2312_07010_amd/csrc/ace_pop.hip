@@ -23,10 +23,10 @@
 // Any step reads each node's 2d+1 populations and writes them: at least
 // 16 (2d+1) bytes of HBM per node update, against 16 for the FD step.
 // Three kernels compute the same result bit for bit: one thread per node
-// (k_pop_direct), a fused tiled march (k_pop_tiled), and the split form, a
-// streaming moment pass (k_pop_moment) followed by an update from phi on
-// cache-line-aligned tiles (k_pop_update), 16 (2d+1) + 16 bytes per node
-// update with aligned streams; the split form is the default for d >= 2.
+// (k_pop_direct); a tiled march on cache-line-aligned tiles that sums phi
+// from the populations itself (k_pop_update, fused: 16 (2d+1) bytes per node
+// update); and the split form, a streaming moment pass (k_pop_moment) then
+// the same tiled update reading phi (16 (2d+1) + 16 bytes).
 #include <math.h>
 #include <string.h>
 
@@ -129,161 +129,13 @@ __global__ __launch_bounds__(256) void k_pop_direct(Shape s, PopCoef c, const do
     for (int k = 0; k < 2 * D + 1; ++k) fout[k * c.ps + i] = out[k];
 }
 
-// ---- tiled (d = 2, 3) ---------------------------------------------------
-// A workgroup of 512 threads owns a 16 x 64 region of the two fastest axes
-// (a wavefront per region row pair) whose interior 14 x 62 nodes it updates;
-// in 3D it marches along axis 0 over a chunk of planes with phi of planes
-// z-1, z, z+1 in registers and phi of plane z in LDS (double-buffered, one
-// barrier per plane).  Loads are unconditional (mapped addresses), so the
-// compiler can keep the next plane's loads in flight over the update.
-constexpr int PX = 64;
-constexpr int PTR = 8;
-constexpr int PRYT = 2;
-constexpr int PRH = PTR * PRYT;  // 16
-constexpr int POX = PX - 2;      // 62
-constexpr int POY = PRH - 2;     // 14
-constexpr int PNT = PX * PTR;    // 512
-constexpr int PLP = PRH * PX;
 // s_waitcnt immediate of vmcnt(0) alone (gfx9 encoding: vmcnt bits 3:0 and
 // 15:14 zero, expcnt 6:4 and lgkmcnt 11:8 at their maxima)
 constexpr int VMCNT0 = 0x0F70;
 
-template <int D, int BC, int NIT>
-__global__ __launch_bounds__(PNT) void k_pop_tiled(Shape s, PopCoef c, const double *__restrict__ fin,
-                                                   double *__restrict__ fout, int tiles_x, int tiles_y,
-                                                   int zchunk)
-{
-    constexpr int Q = 2 * D + 1;
-    __shared__ double L[2 * PLP];
-    const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
-    const int64_t ntile = (int64_t)tiles_x * tiles_y;
-    const int tile = (int)(t % ntile);
-    const int64_t chunk = t / ntile;
-    const int tile_x = tile % tiles_x, tile_y = tile / tiles_x;
-    const int rx = threadIdx.x & (PX - 1);
-    const int tr = threadIdx.x / PX;
-    const int64_t PS = s.M1 * s.M2;
-
-    const int64_t xg = (int64_t)tile_x * POX - 1 + rx;
-    bool zx = false;
-    const int64_t mx = pmap<BC>(xg, s.M2, zx);
-    int64_t off[PRYT], oidx[PRYT];
-    bool zr[PRYT], ok[PRYT];
-#pragma unroll
-    for (int r = 0; r < PRYT; ++r) {
-        const int ry = tr * PRYT + r;
-        const int64_t yg = (int64_t)tile_y * POY - 1 + ry;
-        bool zy = false;
-        const int64_t my = pmap<BC>(yg, s.M1, zy);
-        off[r] = my * s.M2 + mx;
-        zr[r] = zx || zy;
-        ok[r] = ry >= 1 && ry < PRH - 1 && rx >= 1 && rx < PX - 1 && yg >= 0 && yg < s.M1 && xg >= 0 &&
-                xg < s.M2;
-        oidx[r] = ok[r] ? yg * s.M2 + xg : 0;
-    }
-
-    double raw[Q][PRYT];
-    bool zplane = false;
-    auto issue = [&](int64_t zz) {
-        zplane = false;
-        const int64_t base = pmap<BC>(zz, s.M0, zplane) * PS;
-#pragma unroll
-        for (int r = 0; r < PRYT; ++r)
-#pragma unroll
-            for (int k = 0; k < Q; ++k) raw[k][r] = fin[k * c.ps + base + off[r]];
-    };
-    auto consume = [&](double (&ph)[PRYT]) {
-#pragma unroll
-        for (int r = 0; r < PRYT; ++r) {
-            double v = raw[0][r];
-#pragma unroll
-            for (int k = 1; k < Q; ++k) v += raw[k][r];
-            ph[r] = (zplane || zr[r]) ? 0.0 : v;
-        }
-    };
-    // new populations of the owned rows of plane z from phi of planes z-1,
-    // z, z+1 (kept in registers; stored by store_plane)
-    double outv[PRYT][Q];
-    auto update_plane = [&](const double *Lc, const double (&pm)[PRYT], const double (&pc)[PRYT],
-                            const double (&pp)[PRYT]) {
-#pragma unroll
-        for (int r = 0; r < PRYT; ++r) {
-            if (!ok[r]) continue;
-            const int ry = tr * PRYT + r;
-            const double p = pc[r];
-            const double xm = Lc[ry * PX + rx - 1], xp = Lc[ry * PX + rx + 1];
-            const double ym = (r == 0) ? Lc[(ry - 1) * PX + rx] : pc[0];
-            const double yp = (r == PRYT - 1) ? Lc[(ry + 1) * PX + rx] : pc[1];
-            if constexpr (D == 3) {
-                const double lo[3] = {pm[r], ym, xm}, hi[3] = {pp[r], yp, xp};
-                pop_update<3, NIT>(p, lo, hi, c, outv[r]);
-            } else {
-                const double lo[2] = {ym, xm}, hi[2] = {yp, xp};
-                pop_update<2, NIT>(p, lo, hi, c, outv[r]);
-            }
-        }
-    };
-    // The stores follow the wait for the next plane's loads, so that wait
-    // does not also cover them (the outputs are conditional, which keeps the
-    // compiler from counting stores and loads apart).
-    auto store_plane = [&](int64_t z) {
-#pragma unroll
-        for (int r = 0; r < PRYT; ++r) {
-            if (!ok[r]) continue;
-            const int64_t o = z * PS + oidx[r];
-#pragma unroll
-            for (int k = 0; k < Q; ++k) fout[k * c.ps + o] = outv[r][k];
-        }
-    };
-
-    if constexpr (D == 2) {
-        double pc[PRYT];
-        issue(0);
-        consume(pc);
-#pragma unroll
-        for (int r = 0; r < PRYT; ++r) L[(tr * PRYT + r) * PX + rx] = pc[r];
-        __syncthreads();
-        update_plane(L, pc, pc, pc);
-        store_plane(0);
-    } else {
-        const int64_t z0 = chunk * zchunk;
-        const int64_t z1 = std::min<int64_t>(z0 + zchunk, s.M0);
-        double pm[PRYT], pc[PRYT], pp[PRYT], pn[PRYT];
-        issue(z0 - 1);
-        consume(pm);
-        issue(z0);
-        consume(pc);
-        issue(z0 + 1);
-        consume(pp);
-        int b = 0;
-#pragma unroll
-        for (int r = 0; r < PRYT; ++r) L[(tr * PRYT + r) * PX + rx] = pc[r];
-        __syncthreads();
-        for (int64_t z = z0; z < z1; ++z) {
-            // next plane's loads (past the chunk they repeat a valid plane)
-            issue(z + 2 < z1 + 1 ? z + 2 : z1);
-            update_plane(L + b * PLP, pm, pc, pp);
-            // vmcnt(0) here: the loads above and the previous plane's stores
-            // are all that is outstanding (the compiler would otherwise place
-            // the wait after this plane's stores, where it drains them too)
-            __builtin_amdgcn_s_waitcnt(VMCNT0);
-            consume(pn);
-            store_plane(z);
-            b ^= 1;
-#pragma unroll
-            for (int r = 0; r < PRYT; ++r) {
-                pm[r] = pc[r];
-                pc[r] = pp[r];
-                pp[r] = pn[r];
-                L[b * PLP + (tr * PRYT + r) * PX + rx] = pc[r];
-            }
-            __syncthreads();
-        }
-    }
-}
-
-// ---- update from phi (the split form) ------------------------------------
-// Reads phi (written by k_pop_moment) and writes the new populations.  A
+// ---- tiled update (d = 2, 3) ------------------------------------------------
+// Writes the new populations from phi (the split form, phi written by
+// k_pop_moment) or straight from the populations (fused).  A
 // workgroup of 512 threads owns a 16 x 64 output tile aligned to whole cache
 // lines (each wavefront stores 64 consecutive doubles of every population
 // array); phi of the tile plus its one-node ring sits in LDS (18 x 66), the
@@ -301,12 +153,16 @@ constexpr int ULP = ULW * ULH;
 constexpr int UNT = UX * UTR;    // 512
 constexpr int URING = 2 * UX + 2 * UOY;  // 160
 
-template <int D, int BC, int NIT>
-__global__ __launch_bounds__(UNT) void k_pop_update(Shape s, PopCoef c, const double *__restrict__ phi,
+// FUSED: `src` holds the populations and phi of every node the tile needs is
+// summed here from its 2d+1 arrays (k = 0..2d in order, as everywhere);
+// otherwise `src` is phi (written by k_pop_moment).
+template <int D, int BC, int NIT, bool FUSED>
+__global__ __launch_bounds__(UNT) void k_pop_update(Shape s, PopCoef c, const double *__restrict__ src,
                                                     double *__restrict__ fout, int tiles_x, int tiles_y,
                                                     int zchunk)
 {
     constexpr int Q = 2 * D + 1;
+    constexpr int QIN = FUSED ? Q : 1;
     __shared__ double L[2 * ULP];
     const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t ntile = (int64_t)tiles_x * tiles_y;
@@ -358,24 +214,35 @@ __global__ __launch_bounds__(UNT) void k_pop_update(Shape s, PopCoef c, const do
         hslot = ly * ULW + lxx;
     }
 
-    double own_raw[URYT], ring_raw;
+    double own_raw[QIN][URYT], ring_raw[QIN];
     bool zown = false, zring = false;
     auto issue_own = [&](int64_t zz) {
         zown = false;
         const int64_t base = pmap<BC>(zz, s.M0, zown) * PS;
 #pragma unroll
-        for (int r = 0; r < URYT; ++r) own_raw[r] = phi[base + off[r]];
+        for (int r = 0; r < URYT; ++r)
+#pragma unroll
+            for (int k = 0; k < QIN; ++k) own_raw[k][r] = src[k * c.ps + base + off[r]];
     };
     auto issue_ring = [&](int64_t zz) {
         zring = false;
         const int64_t base = pmap<BC>(zz, s.M0, zring) * PS;
-        ring_raw = phi[base + hoff];
+#pragma unroll
+        for (int k = 0; k < QIN; ++k) ring_raw[k] = src[k * c.ps + base + hoff];
     };
-    auto own_val = [&](int r) { return (zown || zr[r]) ? 0.0 : own_raw[r]; };
+    auto own_val = [&](int r) {
+        double v = own_raw[0][r];
+#pragma unroll
+        for (int k = 1; k < QIN; ++k) v += own_raw[k][r];
+        return (zown || zr[r]) ? 0.0 : v;
+    };
     auto stage = [&](double *Lb, const double (&pc)[URYT]) {
 #pragma unroll
         for (int r = 0; r < URYT; ++r) Lb[(1 + tr * URYT + r) * ULW + 1 + lx] = pc[r];
-        if (hslot >= 0) Lb[hslot] = (zring || hz) ? 0.0 : ring_raw;
+        double v = ring_raw[0];
+#pragma unroll
+        for (int k = 1; k < QIN; ++k) v += ring_raw[k];
+        if (hslot >= 0) Lb[hslot] = (zring || hz) ? 0.0 : v;
     };
     double outv[URYT][Q];
     auto update_plane = [&](const double *Lc, const double (&pm)[URYT], const double (&pc)[URYT],
@@ -440,7 +307,10 @@ __global__ __launch_bounds__(UNT) void k_pop_update(Shape s, PopCoef c, const do
             issue_own(z + 2 < z1 + 1 ? z + 2 : z1);
             issue_ring(z + 1 < z1 ? z + 1 : z1 - 1);
             update_plane(L + b * ULP, pm, pc, pp);
-            // vmcnt(0) before this plane's stores (see k_pop_tiled)
+            // vmcnt(0) here: the loads above and the previous plane's stores
+            // are all that is outstanding (the outputs are conditional, so the
+            // compiler would otherwise place the wait after this plane's
+            // stores, where it drains them too)
             __builtin_amdgcn_s_waitcnt(VMCNT0);
             store_plane(z);
             b ^= 1;
@@ -491,21 +361,18 @@ hipError_t launch_pop_t(const Shape &s, const PopCoef &c, const double *fin, dou
         return hipGetLastError();
     }
     if constexpr (D >= 2) {
-        const int tiles_x = (int)((s.M2 + POX - 1) / POX);
-        const int tiles_y = (int)((s.M1 + POY - 1) / POY);
         const int64_t chunks = (D == 3) ? (s.M0 + POP_ZCHUNK - 1) / POP_ZCHUNK : 1;
-        const int64_t nblk = (int64_t)tiles_x * tiles_y * chunks;
+        const int utx = (int)((s.M2 + UX - 1) / UX);
+        const int uty = (int)((s.M1 + UOY - 1) / UOY);
+        const int64_t ublk = (int64_t)utx * uty * chunks;
         if (mode == 1) {
-            hipLaunchKernelGGL((k_pop_tiled<D, BC, NIT>), dim3((unsigned)nblk), dim3(PNT), 0, st, s, c,
-                               fin, fout, tiles_x, tiles_y, POP_ZCHUNK);
+            hipLaunchKernelGGL((k_pop_update<D, BC, NIT, true>), dim3((unsigned)ublk), dim3(UNT), 0, st, s,
+                               c, fin, fout, utx, uty, POP_ZCHUNK);
         } else {
             hipLaunchKernelGGL(k_pop_moment, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, 2 * D + 1,
                                c.ps, n, fin, phi);
-            const int utx = (int)((s.M2 + UX - 1) / UX);
-            const int uty = (int)((s.M1 + UOY - 1) / UOY);
-            const int64_t ublk = (int64_t)utx * uty * chunks;
-            hipLaunchKernelGGL((k_pop_update<D, BC, NIT>), dim3((unsigned)ublk), dim3(UNT), 0, st, s, c, phi,
-                               fout, utx, uty, POP_ZCHUNK);
+            hipLaunchKernelGGL((k_pop_update<D, BC, NIT, false>), dim3((unsigned)ublk), dim3(UNT), 0, st, s,
+                               c, phi, fout, utx, uty, POP_ZCHUNK);
         }
     }
     return hipGetLastError();
@@ -571,8 +438,8 @@ namespace {
 int pop_mode(const ace_pop *P)
 {
     if (P->p.d == 1 || P->kernel == ACE_POP_DIRECT) return 0;
-    if (P->kernel == ACE_POP_FUSED) return 1;
-    return 2;  // split (also the automatic choice for d >= 2)
+    if (P->kernel == ACE_POP_SPLIT) return 2;
+    return 1;  // fused (also the automatic choice for d >= 2)
 }
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
