@@ -347,7 +347,7 @@ def main():
                        "nodes": int(np.prod(w.N)), "monitor_every": 0},
             "roofline": {"bound": "hbm", "achieved": r["roofline_frac"] * HBM_PEAK / 1e9,
                          "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": r["roofline_frac"],
-                         "traffic": None, "kernel": "k_pop_tiled (1 step per launch)",
+                         "traffic": None, "kernel": "k_pop_update, fused (1 step per launch)",
                          "bytes_per_launch": r["bytes_per_update"] * np.prod(w.N),
                          "avg_launch_us": r["avg_launch_us"]},
             "population_rlb": r}), flush=True)
