@@ -349,12 +349,15 @@ int ace_batch_autotune(ace_batch *b, int64_t trial_steps, char *json, size_t cap
 
 /* ---- autotuner ------------------------------------------------------------ */
 
-/* Times each kernel choice (and temporal depth) on the handle's problem for
- * trial_steps steps from the current field, keeps the fastest as the
- * ACE_KERNEL_AUTO choice, restores the field, and writes a one-line JSON
- * record of the timings into json (capacity cap bytes, may be NULL).  If the
- * environment variable ACE_AUTOTUNE_CACHE names a file, the choice is
- * appended there and later handles of the same (d, bc, shape) reuse it. */
+/* Times each kernel choice on the handle's problem for trial_steps steps
+ * from the current field: the one-thread-per-node, LDS-resident (small
+ * fields) and marching kernels, the 3D blocked kernel at several plane chunks
+ * and as a persistent grid, and the 2D blocked kernel at several depths.
+ * Keeps the fastest as the ACE_KERNEL_AUTO choice, restores the field, and
+ * writes a one-line JSON record of the timings into json (capacity cap
+ * bytes, may be NULL).  If the environment variable ACE_AUTOTUNE_CACHE names
+ * a file, the choice is appended there and later handles of the same
+ * (d, bc, shape) reuse it. */
 int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap);
 
 /* Library version string. */
