@@ -27,19 +27,51 @@ __device__ __forceinline__ double approx_rcp(double d)
 // Unique real root of theta + h (theta^3 - theta) = xi for 0 < h < 1.
 // The root map is odd, so the iteration runs on a = |xi| and the sign is
 // restored.  For a <= 1 (always the case under Theorem 2's conditions) it
-// starts from the first-order expansion theta_0 = a + h a (1 - a^2) of the
-// root in h (from theta_0 = a when h > 1/2, where the expansion is poor) and
-// takes `nit` Newton steps on the cubic; the host picks nit by
-// running this same iteration in extended precision over a <= 1.  0 and 1 are
-// exact fixed points of both the start and the step, so 0 and +-1 are
+// starts from the expansion of the root in h, to first order,
+// theta_0 = a - h f(a) = a + h a (1 - a^2), or (c.start2) to second order,
+// theta_0 = a - h f(a) (1 - h f'(a)) with f' = 3 a^2 - 1 (from theta_0 = a
+// when h > 1/2, where the expansion is poor), and takes `nit` Newton steps
+// on the cubic; the host picks the start and nit by running this same
+// iteration in extended precision over a <= 1.  0 and 1 are exact fixed
+// points of both starts and of the step (f(0) = f(1) = 0), so 0 and +-1 are
 // returned exactly.  For a > 1 (only when the conditions fail) the start is
 // a and Newton continues until the correction stops mattering (at most 200
 // steps).
+template <bool S2>
+__device__ __forceinline__ double root_start_t(double a, const StepCoef &c)
+{
+    double x;
+    if (S2) {
+        const double a2 = a * a;
+        const double f = fma(a2, a, -a);        // f(a)
+        const double t = fma(-c.h3, a2, c.oph);  // 1 - h f'(a)
+        x = fma(-(c.h * f), t, a);
+    } else {
+        x = fma(c.h * a, fma(-a, a, 1.0), a);
+    }
+    return (a > 1.0 || c.h > 0.5) ? a : x;
+}
+
+__device__ __forceinline__ double root_start(double a, const StepCoef &c)
+{
+    return c.start2 ? root_start_t<true>(a, c) : root_start_t<false>(a, c);
+}
+
+// Root variants fixed at compile time: RV = NIT + 4 * START2, with NIT = 1..3
+// Newton steps and START2 the second-order start; RV = 0 takes both from the
+// coefficients at run time.  root_variant() gives a launcher the RV of a
+// coefficient set (0 for combinations without an instantiation: the explicit
+// scheme, and nit > 3).
+__host__ __device__ inline int root_variant(const StepCoef &c)
+{
+    if (c.fex || c.nit < 1 || c.nit > 3 || (c.start2 && c.nit == 3)) return 0;
+    return c.nit + 4 * c.start2;
+}
+
 __device__ __forceinline__ double cubic_root(double xi, const StepCoef &c)
 {
     const double a = fabs(xi);
-    double x = fma(c.h * a, fma(-a, a, 1.0), a);
-    if (a > 1.0 || c.h > 0.5) x = a;
+    double x = root_start(a, c);
     for (int k = 0; k < c.nit; ++k) {
         const double x2 = x * x;
         const double p = fma(c.h, fma(x, x2, -x), x - a);
@@ -59,18 +91,19 @@ __device__ __forceinline__ double cubic_root(double xi, const StepCoef &c)
     return copysign(x, xi);
 }
 
-// Same root with the Newton count fixed at compile time (NIT > 0; the
-// iteration and hence every rounding is identical to cubic_root with
-// c.nit == NIT), so the loop unrolls and its constants stay in registers.
-template <int NIT>
+// Same root with the start and the Newton count fixed at compile time
+// (RV > 0, see root_variant; the iteration and hence every rounding is
+// identical to cubic_root with the matching coefficients), so the loop
+// unrolls and its constants stay in registers.
+template <int RV>
 __device__ __forceinline__ double cubic_root_n(double xi, const StepCoef &c)
 {
-    if (NIT <= 0) return cubic_root(xi, c);
+    if (RV <= 0) return cubic_root(xi, c);
+    constexpr int NIT = RV > 0 ? (RV & 3) : 1;
     const double a = fabs(xi);
-    double x = fma(c.h * a, fma(-a, a, 1.0), a);
-    if (a > 1.0 || c.h > 0.5) x = a;
+    double x = root_start_t<(RV >= 4)>(a, c);
 #pragma unroll
-    for (int k = 0; k < (NIT > 0 ? NIT : 1); ++k) {
+    for (int k = 0; k < NIT; ++k) {
         const double x2 = x * x;
         const double p = fma(c.h, fma(x, x2, -x), x - a);
         const double dp = fma(c.h3, x2, c.omh);
@@ -118,11 +151,11 @@ __device__ __forceinline__ double update(double p, double nsum, const StepCoef &
     return cubic_root(explicit_part<D>(p, nsum, c), c);
 }
 
-template <int D, int NIT>
+template <int D, int RV>
 __device__ __forceinline__ double update_n(double p, double nsum, const StepCoef &c)
 {
     if (c.fex) return explicit_fex<D>(p, nsum, c);
-    return cubic_root_n<NIT>(explicit_part<D>(p, nsum, c), c);
+    return cubic_root_n<RV>(explicit_part<D>(p, nsum, c), c);
 }
 
 // Value used for an out-of-range neighbour (rows of the paper's D matrices):

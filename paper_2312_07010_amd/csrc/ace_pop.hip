@@ -50,7 +50,7 @@ struct PopCoef {
 
 // New populations of one node from phi at the node (p) and at its
 // neighbours lo[a] = phi(x - e_a), hi[a] = phi(x + e_a), a = 0..D-1.
-template <int D, int NIT>
+template <int D, int RV>
 __device__ __forceinline__ void pop_update(double p, const double (&lo)[D], const double (&hi)[D],
                                            const PopCoef &c, double (&out)[2 * D + 1])
 {
@@ -65,7 +65,7 @@ __device__ __forceinline__ void pop_update(double p, const double (&lo)[D], cons
     double xi = r[0];
 #pragma unroll
     for (int k = 1; k < 2 * D + 1; ++k) xi += r[k];
-    const double th = cubic_root_n<NIT>(xi, c.sc);
+    const double th = cubic_root_n<RV>(xi, c.sc);
     const double hft = c.sc.h * fma(th, th * th, -th);
     out[0] = fma(-c.w0, hft, r[0]);
 #pragma unroll
@@ -100,7 +100,7 @@ __device__ __forceinline__ int64_t pmap(int64_t c, int64_t n, bool &zero)
 }
 
 // ---- one thread per node (any d; the reference the tiled kernel matches) --
-template <int D, int BC, int NIT>
+template <int D, int BC, int RV>
 __global__ __launch_bounds__(256) void k_pop_direct(Shape s, PopCoef c, const double *__restrict__ fin,
                                                     double *__restrict__ fout)
 {
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void k_pop_direct(Shape s, PopCoef c, const do
         hi[a] = zh ? 0.0 : vh;
     }
     double out[2 * D + 1];
-    pop_update<D, NIT>(p, lo, hi, c, out);
+    pop_update<D, RV>(p, lo, hi, c, out);
 #pragma unroll
     for (int k = 0; k < 2 * D + 1; ++k) fout[k * c.ps + i] = out[k];
 }
@@ -156,7 +156,7 @@ constexpr int URING = 2 * UX + 2 * UOY;  // 160
 // FUSED: `src` holds the populations and phi of every node the tile needs is
 // summed here from its 2d+1 arrays (k = 0..2d in order, as everywhere);
 // otherwise `src` is phi (written by k_pop_moment).
-template <int D, int BC, int NIT, bool FUSED>
+template <int D, int BC, int RV, bool FUSED>
 __global__ __launch_bounds__(UNT) void k_pop_update(Shape s, PopCoef c, const double *__restrict__ src,
                                                     double *__restrict__ fout, int tiles_x, int tiles_y,
                                                     int zchunk)
@@ -257,10 +257,10 @@ __global__ __launch_bounds__(UNT) void k_pop_update(Shape s, PopCoef c, const do
             const double yp = (r == URYT - 1) ? Lc[(ly + 1) * ULW + lxx] : pc[1];
             if constexpr (D == 3) {
                 const double lo[3] = {pm[r], ym, xm}, hi[3] = {pp[r], yp, xp};
-                pop_update<3, NIT>(p, lo, hi, c, outv[r]);
+                pop_update<3, RV>(p, lo, hi, c, outv[r]);
             } else {
                 const double lo[2] = {ym, xm}, hi[2] = {yp, xp};
-                pop_update<2, NIT>(p, lo, hi, c, outv[r]);
+                pop_update<2, RV>(p, lo, hi, c, outv[r]);
             }
         }
     };
@@ -350,13 +350,13 @@ constexpr int POP_ZCHUNK = 64;
 
 // mode: 0 one thread per node; 1 tiled, phi summed in the tile (fused);
 // 2 split: k_pop_moment writes phi to `phi`, then the tiled update reads it.
-template <int D, int BC, int NIT>
+template <int D, int BC, int RV>
 hipError_t launch_pop_t(const Shape &s, const PopCoef &c, const double *fin, double *fout, int mode,
                         double *phi, hipStream_t st)
 {
     const int64_t n = s.M0 * s.M1 * s.M2;
     if (mode == 0 || D == 1) {
-        hipLaunchKernelGGL((k_pop_direct<D, BC, NIT>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+        hipLaunchKernelGGL((k_pop_direct<D, BC, RV>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                            st, s, c, fin, fout);
         return hipGetLastError();
     }
@@ -366,12 +366,12 @@ hipError_t launch_pop_t(const Shape &s, const PopCoef &c, const double *fin, dou
         const int uty = (int)((s.M1 + UOY - 1) / UOY);
         const int64_t ublk = (int64_t)utx * uty * chunks;
         if (mode == 1) {
-            hipLaunchKernelGGL((k_pop_update<D, BC, NIT, true>), dim3((unsigned)ublk), dim3(UNT), 0, st, s,
+            hipLaunchKernelGGL((k_pop_update<D, BC, RV, true>), dim3((unsigned)ublk), dim3(UNT), 0, st, s,
                                c, fin, fout, utx, uty, POP_ZCHUNK);
         } else {
             hipLaunchKernelGGL(k_pop_moment, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, 2 * D + 1,
                                c.ps, n, fin, phi);
-            hipLaunchKernelGGL((k_pop_update<D, BC, NIT, false>), dim3((unsigned)ublk), dim3(UNT), 0, st, s,
+            hipLaunchKernelGGL((k_pop_update<D, BC, RV, false>), dim3((unsigned)ublk), dim3(UNT), 0, st, s,
                                c, phi, fout, utx, uty, POP_ZCHUNK);
         }
     }
@@ -382,10 +382,12 @@ template <int D, int BC>
 hipError_t launch_pop_nit(const Shape &s, const PopCoef &c, const double *fin, double *fout, int mode,
                           double *phi, hipStream_t st)
 {
-    switch (c.sc.nit) {
+    switch (root_variant(c.sc)) {
     case 1: return launch_pop_t<D, BC, 1>(s, c, fin, fout, mode, phi, st);
     case 2: return launch_pop_t<D, BC, 2>(s, c, fin, fout, mode, phi, st);
     case 3: return launch_pop_t<D, BC, 3>(s, c, fin, fout, mode, phi, st);
+    case 5: return launch_pop_t<D, BC, 5>(s, c, fin, fout, mode, phi, st);
+    case 6: return launch_pop_t<D, BC, 6>(s, c, fin, fout, mode, phi, st);
     default: return launch_pop_t<D, BC, 0>(s, c, fin, fout, mode, phi, st);
     }
 }

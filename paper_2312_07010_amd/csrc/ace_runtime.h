@@ -14,13 +14,16 @@ struct Problem {
     double L[3], R[3];
     double dx, dt, eps, kappa, h;
     int nit;
+    int start2;  // second-order start of the root iteration
     int cond_ok;
     int scheme;  // ACE_SCHEME_*
 };
 
 int hip_status(hipError_t e);
 int64_t nodes_per_axis(int64_t N, int bc);
-int newton_iters_for(double h);
+// Newton steps that bring the root iteration (first- or second-order start)
+// within 2^-60 of the root for every |xi| in (0, 1].
+int newton_iters_for(double h, int start2);
 // ACE_OK, ACE_W_CONDITIONS or a negative error.
 int derive(int d, const int64_t *N, const double *L, const double *R, double eps, double dt,
            int bc, Problem &p);

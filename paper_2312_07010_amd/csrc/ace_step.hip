@@ -140,9 +140,9 @@ hipError_t dispatch_direct(const Shape &s, const StepCoef &c, const double *in, 
 constexpr int kResThreads = 1024;
 constexpr int kResNodes = (int)((RESIDENT_MAX + kResThreads - 1) / kResThreads);
 
-// The field alternates between two LDS buffers (one barrier per step); NIT
-// as in update_n (0: the runtime Newton count).
-template <int D, int BC, int NIT>
+// The field alternates between two LDS buffers (one barrier per step); RV
+// is the root variant of update_n (0: start and Newton count at run time).
+template <int D, int BC, int RV>
 __global__ __launch_bounds__(kResThreads) void k_resident(Shape s, StepCoef c,
                                                           double *__restrict__ field,
                                                           int64_t nsteps, int64_t every,
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(kResThreads) void k_resident(Shape s, StepCoef c,
                 double nsum = 0.0;
 #pragma unroll
                 for (int a = 3 - D; a < 3; ++a) nsum += f[nb_lo[k][a]] + f[nb_hi[k][a]];
-                fn[j] = update_n<D, NIT>(p, nsum, c);
+                fn[j] = update_n<D, RV>(p, nsum, c);
             }
         }
         cb ^= 1;
@@ -477,12 +477,16 @@ hipError_t launch_resident(const Shape &s, const StepCoef &c, double *field, int
     hipLaunchKernelGGL((k_resident<DD, BB, NN>), dim3(1), dim3(threads), 0, st, s, c, field, nsteps, \
                        every, mon);                                                              \
     return hipGetLastError();
-#define ACE_RES(DD, BB)                                          \
-    if (s.d == DD && s.bc == BB) {                               \
-        if (!c.fex && c.nit == 1) { ACE_RES_N(DD, BB, 1) }       \
-        if (!c.fex && c.nit == 2) { ACE_RES_N(DD, BB, 2) }       \
-        if (!c.fex && c.nit == 3) { ACE_RES_N(DD, BB, 3) }       \
-        ACE_RES_N(DD, BB, 0)                                     \
+#define ACE_RES(DD, BB)                          \
+    if (s.d == DD && s.bc == BB) {               \
+        switch (root_variant(c)) {               \
+        case 1: { ACE_RES_N(DD, BB, 1) }         \
+        case 2: { ACE_RES_N(DD, BB, 2) }         \
+        case 3: { ACE_RES_N(DD, BB, 3) }         \
+        case 5: { ACE_RES_N(DD, BB, 5) }         \
+        case 6: { ACE_RES_N(DD, BB, 6) }         \
+        default: { ACE_RES_N(DD, BB, 0) }        \
+        }                                        \
     }
     ACE_RES(1, BC_HN) ACE_RES(1, BC_HD) ACE_RES(1, BC_P)
     ACE_RES(2, BC_HN) ACE_RES(2, BC_HD) ACE_RES(2, BC_P)

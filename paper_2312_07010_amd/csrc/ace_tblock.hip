@@ -79,7 +79,7 @@ __device__ __forceinline__ double load_at2(const double *__restrict__ in, int64_
 
 // amdgpu_waves_per_eu(4) caps the kernel at 128 VGPRs, so two 512-thread
 // workgroups (LDS 72 KB each) share a CU.
-template <int BC, bool MON, int NIT>
+template <int BC, bool MON, int RV>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_tblock3d(
     Shape s, StepCoef c, const double *__restrict__ in, double *__restrict__ out,
     double *__restrict__ partials, int tiles_x, int tiles_y, int zchunk)
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             const double ym = (r > 0) ? Q1[r > 0 ? r - 1 : 0] : l0[own[r] - LW];
             const double yp = (r < RYT - 1) ? Q1[r < RYT - 1 ? r + 1 : 0] : l0[own[r] + LW];
             const double nsum = ((Q0[r] + Q2[r]) + (ym + yp)) + (xm + xp);
-            const double v = update_n<3, NIT>(p, nsum, c);
+            const double v = update_n<3, RV>(p, nsum, c);
             W2[r] = v;
             l1w[own[r]] = v;
             if (mon_plane && oof[r] >= 0) {
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 const double ym = l1r[nym[r]];
                 const double yp = l1r[nyp[r]];
                 const double nsum = ((zm + zp) + (ym + yp)) + (xm + xp);
-                const double v = update_n<3, NIT>(p, nsum, c);
+                const double v = update_n<3, RV>(p, nsum, c);
                 if (oof[r] >= 0) orow[oof[r]] = v;
             }
         }
@@ -305,7 +305,7 @@ namespace {
 
 // Workgroups of one kernel instance that fit on the device at once (cached
 // per device and instance; 0 if the query fails).
-template <int BC, bool MON, int NIT>
+template <int BC, bool MON, int RV>
 int64_t resident_blocks()
 {
     static int64_t cache[64] = {};
@@ -313,7 +313,7 @@ int64_t resident_blocks()
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
     if (cache[dev] == 0) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tblock3d<BC, MON, NIT>, NT, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tblock3d<BC, MON, RV>, NT, 0) !=
                 hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             return 0;
@@ -322,7 +322,7 @@ int64_t resident_blocks()
     return cache[dev];
 }
 
-template <int BC, bool MON, int NIT>
+template <int BC, bool MON, int RV>
 hipError_t launch_tb(const Shape &s, const StepCoef &c, const double *in, double *out,
                      double *partials, int64_t *nparts, int zchunk, hipStream_t st)
 {
@@ -332,32 +332,34 @@ hipError_t launch_tb(const Shape &s, const StepCoef &c, const double *in, double
     if (zchunk > 0) {
         nblk = (int64_t)tiles_x * tiles_y * ((s.M0 + zchunk - 1) / zchunk);
     } else {
-        const int64_t res = resident_blocks<BC, MON, NIT>();
+        const int64_t res = resident_blocks<BC, MON, RV>();
         if (res <= 0) return hipErrorInvalidValue;
         nblk = std::min<int64_t>(res, tblock_partials_needed(s, 0));
     }
     if (nparts) *nparts = nblk;
-    hipLaunchKernelGGL((k_tblock3d<BC, MON, NIT>), dim3((unsigned)nblk), dim3(NT), 0, st, s, c, in,
+    hipLaunchKernelGGL((k_tblock3d<BC, MON, RV>), dim3((unsigned)nblk), dim3(NT), 0, st, s, c, in,
                        out, partials, tiles_x, tiles_y, zchunk);
     return hipGetLastError();
 }
 
-template <int BC, int NIT>
+template <int BC, int RV>
 hipError_t launch_tb_mon(const Shape &s, const StepCoef &c, const double *in, double *out,
                          double *partials, int64_t *nparts, int zchunk, hipStream_t st)
 {
-    return partials ? launch_tb<BC, true, NIT>(s, c, in, out, partials, nparts, zchunk, st)
-                    : launch_tb<BC, false, NIT>(s, c, in, out, partials, nparts, zchunk, st);
+    return partials ? launch_tb<BC, true, RV>(s, c, in, out, partials, nparts, zchunk, st)
+                    : launch_tb<BC, false, RV>(s, c, in, out, partials, nparts, zchunk, st);
 }
 
 template <int BC>
 hipError_t launch_tb_nit(const Shape &s, const StepCoef &c, const double *in, double *out,
                          double *partials, int64_t *nparts, int zchunk, hipStream_t st)
 {
-    switch (c.nit) {
+    switch (root_variant(c)) {
     case 1: return launch_tb_mon<BC, 1>(s, c, in, out, partials, nparts, zchunk, st);
     case 2: return launch_tb_mon<BC, 2>(s, c, in, out, partials, nparts, zchunk, st);
     case 3: return launch_tb_mon<BC, 3>(s, c, in, out, partials, nparts, zchunk, st);
+    case 5: return launch_tb_mon<BC, 5>(s, c, in, out, partials, nparts, zchunk, st);
+    case 6: return launch_tb_mon<BC, 6>(s, c, in, out, partials, nparts, zchunk, st);
     default: return launch_tb_mon<BC, 0>(s, c, in, out, partials, nparts, zchunk, st);
     }
 }

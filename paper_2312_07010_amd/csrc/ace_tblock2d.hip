@@ -94,9 +94,9 @@ __device__ __forceinline__ void yoffs(const Shape &s, const Geo &g, int ry, int 
     (void)tx;
 }
 
-// NIT > 0: the Newton count fixed at compile time (unrolled; identical
-// rounding to the runtime count, see cubic_root_n); 0: the runtime count.
-template <int BC, bool MON, bool LEVELS, int NIT>
+// RV: the root variant of cubic_root_n (start and Newton count fixed at
+// compile time, identical rounding to the run-time path; 0: run time).
+template <int BC, bool MON, bool LEVELS, int RV>
 __global__ __launch_bounds__(BNT) void k_tblock2d(Shape s, StepCoef c, const double *__restrict__ in,
                                                   double *__restrict__ out,
                                                   double *__restrict__ partials, int K, int tiles_x,
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(BNT) void k_tblock2d(Shape s, StepCoef c, const dou
             const int o = (ry + 1) * BLW + tx + 1;
             const double p = src[o];
             const double nsum = (src[o + ym] + src[o + yp]) + (src[o + g.xm] + src[o + g.xp]);
-            const double v = update_n<2, NIT>(p, nsum, c);
+            const double v = update_n<2, RV>(p, nsum, c);
             dst[o] = v;
             if (LEVELS || k == K) {
                 const int64_t yg = g.y0r + ry;
@@ -289,18 +289,18 @@ int64_t tblock2d_blocks(const Shape &s, int K)
 
 namespace {
 
-template <int BC, int NIT>
+template <int BC, int RV>
 hipError_t launch_t2(const Shape &s, const StepCoef &c, const double *in, double *out, double *partials,
                      int K, int tiles_x, int ntiles, int64_t level_stride, bool levels, hipStream_t st)
 {
     if (partials)
-        hipLaunchKernelGGL((k_tblock2d<BC, true, false, NIT>), dim3(ntiles), dim3(BNT), 0, st, s, c, in,
+        hipLaunchKernelGGL((k_tblock2d<BC, true, false, RV>), dim3(ntiles), dim3(BNT), 0, st, s, c, in,
                            out, partials, K, tiles_x, level_stride);
     else if (levels)
-        hipLaunchKernelGGL((k_tblock2d<BC, false, true, NIT>), dim3(ntiles), dim3(BNT), 0, st, s, c, in,
+        hipLaunchKernelGGL((k_tblock2d<BC, false, true, RV>), dim3(ntiles), dim3(BNT), 0, st, s, c, in,
                            out, partials, K, tiles_x, level_stride);
     else
-        hipLaunchKernelGGL((k_tblock2d<BC, false, false, NIT>), dim3(ntiles), dim3(BNT), 0, st, s, c, in,
+        hipLaunchKernelGGL((k_tblock2d<BC, false, false, RV>), dim3(ntiles), dim3(BNT), 0, st, s, c, in,
                            out, partials, K, tiles_x, level_stride);
     return hipGetLastError();
 }
@@ -310,15 +310,17 @@ hipError_t launch_t2_nit(const Shape &s, const StepCoef &c, const double *in, do
                          double *partials, int K, int tiles_x, int ntiles, int64_t level_stride,
                          bool levels, hipStream_t st)
 {
-    const int nit = c.fex ? 0 : c.nit;
+    const int rv = root_variant(c);
     auto go = [&](auto tag) {
         return launch_t2<BC, decltype(tag)::value>(s, c, in, out, partials, K, tiles_x, ntiles, level_stride,
                                                    levels, st);
     };
-    switch (nit) {
+    switch (rv) {
     case 1: return go(std::integral_constant<int, 1>());
     case 2: return go(std::integral_constant<int, 2>());
     case 3: return go(std::integral_constant<int, 3>());
+    case 5: return go(std::integral_constant<int, 5>());
+    case 6: return go(std::integral_constant<int, 6>());
     default: return go(std::integral_constant<int, 0>());
     }
 }
