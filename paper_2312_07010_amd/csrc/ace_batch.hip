@@ -4,8 +4,10 @@
 // counter; tasks are instances ordered by decreasing cost, so the largest
 // start first) and runs every step of that instance before taking another.
 // Instances whose field fits in LDS are stepped entirely in LDS (one global
-// read and one write per launch); larger ones ping-pong between their two
-// arena slots with a workgroup barrier between steps.  Every instance carries
+// read and one write per launch).  Larger 2D ones advance in rounds of up to
+// four steps over 32 x 64 LDS regions (temporal blocking, one global read and
+// write per round); larger 1D ones ping-pong between their two arena slots
+// with a workgroup barrier between steps.  Every instance carries
 // its own shape, boundary condition, kappa, h and Newton count, and every
 // update uses the same arithmetic as the single-instance kernels, so each
 // instance's result equals ace_step on that instance bit for bit.
@@ -26,6 +28,7 @@
 #include "../../include/ace.h"
 #include "ace_device.h"
 #include "ace_runtime.h"
+#include "ace_tile2d.h"
 
 namespace ace {
 
@@ -145,6 +148,83 @@ __device__ void batch_stream(const BatchInst &I, double *__restrict__ fa, double
     }
 }
 
+// 2D instance too large for LDS, advanced in rounds of up to kTK steps: each
+// round walks the instance's 32 x 64 regions (ring of K nodes), advances each
+// region K levels in LDS (the two padded planes live in the workgroup's LDS
+// array) and writes its tile interior to the other arena slot; a workgroup
+// barrier (with its memory fence) separates the rounds.  The arithmetic and
+// neighbour order are those of the single-instance kernels.
+constexpr int kTK = 4;
+
+template <int BC>
+__device__ void batch_tiles2d(const BatchInst &I, double *__restrict__ fa, double *__restrict__ fb,
+                              int64_t nsteps, double *lds)
+{
+    using namespace tile2d;
+    constexpr int TR = kBT / BX;  // thread rows
+    constexpr int RT = BH / TR;   // region rows per thread
+    static_assert(2 * BLP <= RESIDENT_MAX + 1, "two padded planes must fit the LDS array");
+    Shape s;
+    s.d = 2;
+    s.bc = BC;
+    s.M0 = 1;
+    s.M1 = I.M1;
+    s.M2 = I.M2;
+    const int tx = threadIdx.x & (BX - 1), tr = threadIdx.x / BX;
+    double *F = lds;
+    for (int i = threadIdx.x; i < 2 * BLP; i += kBT) F[i] = 0.0;  // zero pads
+    __syncthreads();
+    int64_t done = 0;
+    int par = 0;  // 0: the field is in fa
+    while (done < nsteps) {
+        const int K = (int)std::min<int64_t>(kTK, nsteps - done);
+        const double *__restrict__ in = par ? fb : fa;
+        double *__restrict__ out = par ? fa : fb;
+        const int64_t tiles_x = (s.M2 + BX - 2 * K - 1) / (BX - 2 * K);
+        const int64_t tiles_y = (s.M1 + BH - 2 * K - 1) / (BH - 2 * K);
+        for (int64_t t = 0; t < tiles_x * tiles_y; ++t) {
+            const Geo g = make_geo<BC>(s, K, tiles_x, t, tx);
+            const bool xin = g.xg >= 0 && g.xg < s.M2 && tx >= K && tx < BX - K;
+#pragma unroll
+            for (int j = 0; j < RT; ++j) {
+                const int ry = tr + TR * j;
+                const int64_t o = goff<BC>(s, g.y0r + ry, g.xg);
+                F[(ry + 1) * BLW + tx + 1] = (o < 0) ? 0.0 : in[o];
+            }
+            __syncthreads();
+            for (int k = 1; k <= K; ++k) {
+                const double *src = F + ((k - 1) & 1) * BLP;
+                double *dst = F + (k & 1) * BLP;
+#pragma unroll
+                for (int j = 0; j < RT; ++j) {
+                    const int ry = tr + TR * j;
+                    if (ry < k || ry >= BH - k) continue;  // wave-uniform
+                    int ym, yp;
+                    yoffs<BC>(s, g, ry, ym, yp);
+                    const int o = (ry + 1) * BLW + tx + 1;
+                    const double p = src[o];
+                    const double nsum = (src[o + ym] + src[o + yp]) + (src[o + g.xm] + src[o + g.xp]);
+                    const double v = update<2>(p, nsum, I.c);
+                    dst[o] = v;
+                    const int64_t yg = g.y0r + ry;
+                    if (k == K && xin && ry >= K && ry < BH - K && yg >= 0 && yg < s.M1)
+                        out[yg * s.M2 + g.xg] = v;
+                }
+                __syncthreads();
+            }
+        }
+        __threadfence_block();
+        __syncthreads();
+        done += K;
+        par ^= 1;
+    }
+    if (par) {  // result back into the first arena
+        for (int64_t j = threadIdx.x; j < s.M1 * s.M2; j += kBT) fa[j] = fb[j];
+        __threadfence_block();
+        __syncthreads();
+    }
+}
+
 __global__ void k_batch_reset(int *counter)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0;
@@ -181,9 +261,9 @@ __global__ __launch_bounds__(kBT) void k_batch(const BatchInst *__restrict__ ins
             else if (I.bc == BC_HD) batch_stream<1, BC_HD>(I, fa, fb, nsteps);
             else batch_stream<1, BC_P>(I, fa, fb, nsteps);
         } else {
-            if (I.bc == BC_HN) batch_stream<2, BC_HN>(I, fa, fb, nsteps);
-            else if (I.bc == BC_HD) batch_stream<2, BC_HD>(I, fa, fb, nsteps);
-            else batch_stream<2, BC_P>(I, fa, fb, nsteps);
+            if (I.bc == BC_HN) batch_tiles2d<BC_HN>(I, fa, fb, nsteps, f);
+            else if (I.bc == BC_HD) batch_tiles2d<BC_HD>(I, fa, fb, nsteps, f);
+            else batch_tiles2d<BC_P>(I, fa, fb, nsteps, f);
         }
     }
 }

@@ -22,77 +22,17 @@
 #include <type_traits>
 
 #include "ace_device.h"
+#include "ace_tile2d.h"
 
 namespace ace {
 
 namespace {
 
-constexpr int BX = 64;           // region width (one wavefront)
+using namespace tile2d;
+
 constexpr int BTR = 8;           // thread rows
-constexpr int BH = 32;           // region height
 constexpr int BRT = BH / BTR;    // rows per thread
 constexpr int BNT = BX * BTR;    // 512 threads
-constexpr int BLW = BX + 2;      // padded LDS row
-constexpr int BLH = BH + 2;
-constexpr int BLP = BLW * BLH;
-
-template <int BC>
-__device__ __forceinline__ int64_t map2(int64_t c, int64_t n)
-{
-    if (c >= 0 && c < n) return c;
-    if (BC == BC_HN) return c < 0 ? 0 : n - 1;
-    if (BC == BC_HD) return -1;
-    const int64_t r = c % n;  // periodic: the ring may wrap more than once on tiny grids
-    return r < 0 ? r + n : r;
-}
-
-// Global offset of region slot (y, x) BC-mapped, or -1 for the Dirichlet 0.
-template <int BC>
-__device__ __forceinline__ int64_t goff(const Shape &s, int64_t y, int64_t x)
-{
-    const int64_t my = map2<BC>(y, s.M1), mx = map2<BC>(x, s.M2);
-    return (my < 0 || mx < 0) ? -1 : my * s.M2 + mx;
-}
-
-// Per-thread geometry shared by both kernels.
-struct Geo {
-    int64_t y0r, xg;  // global coordinates of region row 0 / this lane's column
-    int K;
-    int xm, xp;       // LDS column offsets of the x neighbours (BC-redirected)
-};
-
-template <int BC>
-__device__ __forceinline__ Geo make_geo(const Shape &s, int K, int tiles_x)
-{
-    Geo g;
-    const int tile = (int)xcd_tile(blockIdx.x, gridDim.x);  // XCD-aware numbering
-    const int tx = threadIdx.x & (BX - 1);
-    const int oy = BH - 2 * K, ox = BX - 2 * K;
-    g.y0r = (int64_t)(tile / tiles_x) * oy - K;
-    g.xg = (int64_t)(tile % tiles_x) * ox - K + tx;
-    g.K = K;
-    g.xm = -1;
-    g.xp = 1;
-    if (BC != BC_P) {
-        if (g.xg == 0) g.xm = (BC == BC_HN) ? 0 : -(tx + 1);          // own slot / pad column
-        if (g.xg == s.M2 - 1) g.xp = (BC == BC_HN) ? 0 : (BX - tx);  // own slot / pad column
-    }
-    return g;
-}
-
-// LDS neighbour offsets of region row ry (BC-redirected in y).
-template <int BC>
-__device__ __forceinline__ void yoffs(const Shape &s, const Geo &g, int ry, int tx, int &ym, int &yp)
-{
-    ym = -BLW;
-    yp = BLW;
-    if (BC != BC_P) {
-        const int64_t yg = g.y0r + ry;
-        if (yg == 0) ym = (BC == BC_HN) ? 0 : -(ry + 1) * BLW;             // own slot / pad row 0
-        if (yg == s.M1 - 1) yp = (BC == BC_HN) ? 0 : (BH - ry) * BLW;     // own slot / pad row
-    }
-    (void)tx;
-}
 
 // RV: the root variant of cubic_root_n (start and Newton count fixed at
 // compile time, identical rounding to the run-time path; 0: run time).
@@ -106,7 +46,7 @@ __global__ __launch_bounds__(BNT) void k_tblock2d(Shape s, StepCoef c, const dou
     __shared__ double red[3 * (BNT / 64)];
     const int tx = threadIdx.x & (BX - 1);
     const int tr = threadIdx.x / BX;
-    const Geo g = make_geo<BC>(s, K, tiles_x);
+    const Geo g = make_geo<BC>(s, K, tiles_x, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x & (BX - 1));
     for (int i = threadIdx.x; i < 2 * BLP; i += BNT) F[i] = 0.0;
     __syncthreads();
     // level 0 into buffer 0
@@ -149,7 +89,7 @@ __global__ __launch_bounds__(BNT) void k_tblock2d(Shape s, StepCoef c, const dou
             const int ry = tr + BTR * j;
             if (ry < k || ry >= BH - k) continue;  // wave-uniform
             int ym, yp;
-            yoffs<BC>(s, g, ry, tx, ym, yp);
+            yoffs<BC>(s, g, ry, ym, yp);
             const int o = (ry + 1) * BLW + tx + 1;
             const double p = src[o];
             const double nsum = (src[o + ym] + src[o + yp]) + (src[o + g.xm] + src[o + g.xp]);
@@ -191,7 +131,7 @@ __global__ __launch_bounds__(BNT) void k_adjoint_tb2d(Shape s, StepCoef c,
     __shared__ double red[BNT / 64];
     const int tx = threadIdx.x & (BX - 1);
     const int tr = threadIdx.x / BX;
-    const Geo g = make_geo<BC>(s, K, tiles_x);
+    const Geo g = make_geo<BC>(s, K, tiles_x, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x & (BX - 1));
     for (int i = threadIdx.x; i < BLP; i += BNT) {
         MU[i] = 0.0;
         P[i] = 0.0;
@@ -234,7 +174,7 @@ __global__ __launch_bounds__(BNT) void k_adjoint_tb2d(Shape s, StepCoef c,
             const int ry = tr + BTR * j;
             if (ry < lvl + 1 || ry >= BH - lvl - 1) continue;
             int ym, yp;
-            yoffs<BC>(s, g, ry, tx, ym, yp);
+            yoffs<BC>(s, g, ry, ym, yp);
             const int o = (ry + 1) * BLW + tx + 1;
             const double mu = MU[o];
             const double p = p0[o];
