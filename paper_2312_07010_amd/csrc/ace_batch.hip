@@ -182,16 +182,26 @@ __device__ void batch_tiles2d(const BatchInst &I, double *__restrict__ fa, doubl
         double *__restrict__ out = par ? fa : fb;
         const int64_t tiles_x = (s.M2 + BX - 2 * K - 1) / (BX - 2 * K);
         const int64_t tiles_y = (s.M1 + BH - 2 * K - 1) / (BH - 2 * K);
-        for (int64_t t = 0; t < tiles_x * tiles_y; ++t) {
+        const int64_t ntiles = tiles_x * tiles_y;
+        // the next region's values are loaded into registers while the
+        // current region advances, and staged after its last level
+        double nxt[RT];
+        auto fetch = [&](int64_t t) {
+            const Geo gn = make_geo<BC>(s, K, tiles_x, t, tx);
+#pragma unroll
+            for (int j = 0; j < RT; ++j) {
+                const int64_t o = goff<BC>(s, gn.y0r + tr + TR * j, gn.xg);
+                nxt[j] = (o < 0) ? 0.0 : in[o];
+            }
+        };
+        fetch(0);
+        for (int64_t t = 0; t < ntiles; ++t) {
             const Geo g = make_geo<BC>(s, K, tiles_x, t, tx);
             const bool xin = g.xg >= 0 && g.xg < s.M2 && tx >= K && tx < BX - K;
 #pragma unroll
-            for (int j = 0; j < RT; ++j) {
-                const int ry = tr + TR * j;
-                const int64_t o = goff<BC>(s, g.y0r + ry, g.xg);
-                F[(ry + 1) * BLW + tx + 1] = (o < 0) ? 0.0 : in[o];
-            }
+            for (int j = 0; j < RT; ++j) F[(tr + TR * j + 1) * BLW + tx + 1] = nxt[j];
             __syncthreads();
+            if (t + 1 < ntiles) fetch(t + 1);
             for (int k = 1; k <= K; ++k) {
                 const double *src = F + ((k - 1) & 1) * BLP;
                 double *dst = F + (k & 1) * BLP;
