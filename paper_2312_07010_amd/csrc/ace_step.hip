@@ -241,8 +241,11 @@ __global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ part
 }
 
 // Per-block partial sums of (1 + phi)/2 (the smooth phase indicator), each
-// block over a contiguous range in a fixed order.
-constexpr int kPhaseBlocks = 1024;
+// block over a contiguous range in a fixed order: every thread keeps
+// kPhaseU running sums over loads kPhaseU * 256 apart (so kPhaseU loads are
+// in flight per thread), added in order at the end.
+constexpr int kPhaseBlocks = 4096;
+constexpr int kPhaseU = 8;
 __global__ __launch_bounds__(256) void k_phase_partials(const double *__restrict__ f, int64_t n,
                                                         double *__restrict__ part)
 {
@@ -250,8 +253,18 @@ __global__ __launch_bounds__(256) void k_phase_partials(const double *__restrict
     const int64_t per = (n + gridDim.x - 1) / gridDim.x;
     const int64_t lo = (int64_t)blockIdx.x * per;
     const int64_t hi = (lo + per < n) ? lo + per : n;
-    double v = 0.0;
-    for (int64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) v += 0.5 * (1.0 + f[j]);
+    double acc[kPhaseU];
+#pragma unroll
+    for (int u = 0; u < kPhaseU; ++u) acc[u] = 0.0;
+    int64_t j = lo + threadIdx.x;
+    for (; j + (kPhaseU - 1) * 256 < hi; j += kPhaseU * 256) {
+#pragma unroll
+        for (int u = 0; u < kPhaseU; ++u) acc[u] += 0.5 * (1.0 + f[j + u * 256]);
+    }
+    for (; j < hi; j += 256) acc[0] += 0.5 * (1.0 + f[j]);
+    double v = acc[0];
+#pragma unroll
+    for (int u = 1; u < kPhaseU; ++u) v += acc[u];
     v = wave_sum(v);
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -292,22 +305,28 @@ hipError_t launch_step_direct(const Shape &s, const StepCoef &c, const double *i
 // 256-thread workgroup owns 16 rows x 64 columns of the two fastest axes and
 // a chunk of MZ planes, so the grid (and the partials the one-block
 // reduction then reads) is small.  The per-node terms are those of k_monitor
-// in the same order; the +x and +y neighbours come from loads at wrapped or
-// clamped coordinates (always valid, so every load is unconditional) and +z
-// from the next plane, which the march loads anyway.
+// in the same order.  Each node is loaded once: one wavefront holds 64
+// consecutive columns of MRY rows, the +x neighbour comes from the next lane
+// (the column after the tile from one extra load, by lanes 0..MRY-1), the
+// +y neighbour from the thread's next row (the row after its MRY rows from
+// one extra load), the +z neighbour from the next plane.  Loads for plane
+// z + 2 are issued while plane z is summed.  Past the field's end the extra
+// loads read wrapped or clamped (always valid) coordinates, so every load is
+// unconditional; HN and HD then replace the value as the BC requires.
 // ---------------------------------------------------------------------------
-constexpr int MTX = 64;
+constexpr int MTX = 64;  // one wavefront across the columns of a tile
 constexpr int MTR = 4;
 constexpr int MRY = 4;
 constexpr int MTY = MTR * MRY;  // 16 rows per tile
 constexpr int MNT = MTX * MTR;  // 256 threads
-constexpr int MZ = 64;
+constexpr int MZ = 32;
 
 template <int D, int BC>
 __global__ __launch_bounds__(MNT) void k_monitor_tiles(Shape s, const double *__restrict__ in,
                                                       double *__restrict__ partials, int tiles_x,
                                                       int tiles_y)
 {
+    static_assert(MTX == 64, "the +x neighbour is taken from the next lane of the wavefront");
     __shared__ double lds[3 * (MNT / 64)];
     const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t ntile = (int64_t)tiles_x * tiles_y;
@@ -315,45 +334,71 @@ __global__ __launch_bounds__(MNT) void k_monitor_tiles(Shape s, const double *__
     const int64_t chunk = t / ntile;
     const int lane = threadIdx.x & (MTX - 1);
     const int tr = threadIdx.x / MTX;
-    const int64_t x = (int64_t)(tile % tiles_x) * MTX + lane;
+    const int64_t x0 = (int64_t)(tile % tiles_x) * MTX;
+    const int64_t x = x0 + lane;
     const int64_t ybase = (int64_t)(tile / tiles_x) * MTY + tr * MRY;
     const int64_t PS = s.M1 * s.M2;
     const bool xin = x < s.M2;
     const int64_t cx = xin ? x : s.M2 - 1;
     const bool xlast = x + 1 >= s.M2;
-    const int64_t xn = xlast ? (BC == BC_P ? 0 : cx) : x + 1;  // wrap index for periodic
-    int64_t row[MRY], rown[MRY];
+    const bool x_from_edge = xlast || lane == MTX - 1;
+    // column after the tile and row after the thread's rows (wrapped past the end)
+    const int64_t xe = (x0 + MTX < s.M2) ? x0 + MTX : 0;
+    const int64_t ye = ((ybase + MRY < s.M1) ? ybase + MRY : 0) * s.M2;
+    int64_t row[MRY];
     bool yin[MRY], ylast[MRY];
 #pragma unroll
     for (int r = 0; r < MRY; ++r) {
         const int64_t y = ybase + r;
         yin[r] = y < s.M1;
-        const int64_t cy = yin[r] ? y : s.M1 - 1;
         ylast[r] = y + 1 >= s.M1;
-        row[r] = cy * s.M2;
-        rown[r] = (ylast[r] ? (BC == BC_P ? 0 : cy) : y + 1) * s.M2;
+        row[r] = (yin[r] ? y : s.M1 - 1) * s.M2;
     }
+    // lane r < MRY loads the edge column of row r
+    const int er = lane < MRY ? lane : MRY - 1;
+    const int64_t eoff = (ybase + er < s.M1 ? ybase + er : s.M1 - 1) * s.M2 + xe;
+    auto zmap = [&](int64_t zz) -> int64_t {  // plane index past the end: wrapped, then clamped
+        if (zz < s.M0) return zz;
+        zz -= s.M0;
+        return zz < s.M0 ? zz : s.M0 - 1;
+    };
     const int64_t z0 = chunk * MZ;
     const int64_t z1 = (z0 + MZ < s.M0) ? z0 + MZ : s.M0;
     MonAcc m;
     mon_zero(m);
-    double cur[MRY];
+    double cur[MRY], nxt[MRY], cye, cxe, nye = 0.0, nxe = 0.0;
+    {
+        const int64_t zb = z0 * PS;
 #pragma unroll
-    for (int r = 0; r < MRY; ++r) cur[r] = in[z0 * PS + row[r] + cx];
-    for (int64_t z = z0; z < z1; ++z) {
-        const bool zlast = z + 1 >= s.M0;
-        const int64_t zn = zlast ? (BC == BC_P ? 0 : z) : z + 1;
-        double nxt[MRY], vx[MRY], vy[MRY];
+        for (int r = 0; r < MRY; ++r) cur[r] = in[zb + row[r] + cx];
+        cye = in[zb + ye + cx];
+        cxe = in[zb + eoff];
+        if (D == 3) {
+            const int64_t zn = zmap(z0 + 1) * PS;
 #pragma unroll
-        for (int r = 0; r < MRY; ++r) {
-            nxt[r] = in[zn * PS + row[r] + cx];
-            vx[r] = in[z * PS + row[r] + xn];
-            vy[r] = in[z * PS + rown[r] + cx];
+            for (int r = 0; r < MRY; ++r) nxt[r] = in[zn + row[r] + cx];
+            nye = in[zn + ye + cx];
+            nxe = in[zn + eoff];
         }
+    }
+    for (int64_t z = z0; z < z1; ++z) {
+        double nn[MRY], nnye = 0.0, nnxe = 0.0;
+        if (D == 3) {
+            const int64_t z2 = zmap(z + 2) * PS;
+#pragma unroll
+            for (int r = 0; r < MRY; ++r) nn[r] = in[z2 + row[r] + cx];
+            nnye = in[z2 + ye + cx];
+            nnxe = in[z2 + eoff];
+        }
+        const bool zlast = z + 1 >= s.M0;
 #pragma unroll
         for (int r = 0; r < MRY; ++r) {
-            if (!(xin && yin[r])) continue;
             const double p = cur[r];
+            const double from_lane = __shfl_down(p, 1, 64);
+            const double from_edge = __shfl(cxe, r, 64);
+            const double vx = x_from_edge ? from_edge : from_lane;
+            const double vy = (ylast[r] || r == MRY - 1) ? cye : cur[r + 1 < MRY ? r + 1 : r];
+            if (!(xin && yin[r])) continue;
             double grad = 0.0;
             if (D == 3) {
                 const double hi = zlast ? outside<BC>(p, nxt[r]) : nxt[r];
@@ -362,13 +407,13 @@ __global__ __launch_bounds__(MNT) void k_monitor_tiles(Shape s, const double *__
                 if (BC == BC_HD && z == 0) grad = fma(p, p, grad);
             }
             {
-                const double hi = ylast[r] ? outside<BC>(p, vy[r]) : vy[r];
+                const double hi = ylast[r] ? outside<BC>(p, vy) : vy;
                 const double dh = hi - p;
                 grad = fma(dh, dh, grad);
                 if (BC == BC_HD && ybase + r == 0) grad = fma(p, p, grad);
             }
             {
-                const double hi = xlast ? outside<BC>(p, vx[r]) : vx[r];
+                const double hi = xlast ? outside<BC>(p, vx) : vx;
                 const double dh = hi - p;
                 grad = fma(dh, dh, grad);
                 if (BC == BC_HD && x == 0) grad = fma(p, p, grad);
@@ -377,8 +422,17 @@ __global__ __launch_bounds__(MNT) void k_monitor_tiles(Shape s, const double *__
             m.grad += grad;
             m.mx = nan_max(m.mx, fabs(p));
         }
+        if (D == 3) {
 #pragma unroll
-        for (int r = 0; r < MRY; ++r) cur[r] = nxt[r];
+            for (int r = 0; r < MRY; ++r) {
+                cur[r] = nxt[r];
+                nxt[r] = nn[r];
+            }
+            cye = nye;
+            cxe = nxe;
+            nye = nnye;
+            nxe = nnxe;
+        }
     }
     block_reduce_store(m, lds, partials + 3 * blockIdx.x);
 }

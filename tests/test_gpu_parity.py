@@ -105,6 +105,31 @@ def test_energy_of_oracle_field_isolates_reduction(ace, orc):
         assert s.maxnorm() == p.maxnorm(phi)
 
 
+@pytest.mark.parametrize("bc", [0, 1, 2])
+@pytest.mark.parametrize("M", [(5, 3), (16, 64), (17, 65), (35, 300), (4, 16, 64), (21, 35, 129),
+                               (33, 8, 128), (3, 3, 3)])
+def test_standalone_monitor_on_tile_edges(ace, orc, bc, M):
+    """Energy and max-norm of a given field (no step) for stored extents at,
+    one past and below the monitor tile's 64 columns and 4-row groups, where
+    the +x and +y neighbours switch from the next lane or row to the wrapped
+    or boundary value."""
+    M = list(M)
+    N = [m + {0: -2, 1: 1, 2: 0}[bc] for m in M]
+    if min(N) < {0: 1, 1: 2, 2: 3}[bc]:
+        pytest.skip("too few nodes for this BC")
+    d = len(M)
+    dx = 1.0 / 64
+    R = [n * dx for n in N]
+    eps = math.sqrt(0.1 * dx * dx / 1e-3)
+    s = ace.Solver(d, N, [0.0] * d, R, eps, 1e-3, bc)
+    p = orc.Problem(d, N, [0.0] * d, R, eps, 1e-3, bc)
+    assert list(s.shape) == M
+    phi = np.random.default_rng(sum(M) + 10 * bc).uniform(-1, 1, p.shape)
+    s.set_phi0(phi)
+    assert s.energy() == pytest.approx(p.energy(phi), rel=1e-14)
+    assert s.maxnorm() == p.maxnorm(phi)
+
+
 def test_edge_cases(ace, orc):
     # smallest grids of each BC, fixed points, signed zero, |phi0| > 1 warning
     for d, bc, N in ((1, 1, 2), (2, 1, 2), (3, 1, 2), (1, 0, 1), (3, 0, 1), (1, 2, 3), (3, 2, 3)):
