@@ -27,8 +27,10 @@ def _args(d, N, bc, kappa, dt=2e-3, dx=None):
     return (d, N, [0.0] * d, [n * dx for n in N], eps, dt, bc)
 
 
+# the 3D shapes span several 16 x 128 tiles with ragged edges; 300 planes make
+# three 128-plane chunks, the last one ragged
 SHAPES = [(1, (3,)), (1, (300,)), (1, (2500,)), (2, (3, 5)), (2, (40, 61)), (2, (100, 130)),
-          (3, (3, 4, 5)), (3, (21, 35, 129)), (3, (70, 20, 64))]
+          (3, (3, 4, 5)), (3, (21, 35, 129)), (3, (70, 20, 64)), (3, (300, 20, 140))]
 
 
 @pytest.mark.parametrize("bc", [0, 1, 2])
