@@ -317,8 +317,8 @@ typedef struct {
 /* Creates a batch of count instances (each validated as ace_create does;
  * status[i] receives each instance's status when status is not NULL).
  * Allocates one device arena for all fields.  Instances of one batch run in
- * one persistent launch: workgroups take (instance, tile) tasks from a queue
- * ordered by decreasing cost. */
+ * one persistent launch: each workgroup takes whole instances, one at a
+ * time, from a queue ordered by decreasing cost, and runs all their steps. */
 int ace_batch_create(int count, const ace_instance_desc *desc,
                      ace_batch **out, int *status);
 int ace_batch_destroy(ace_batch *b);
