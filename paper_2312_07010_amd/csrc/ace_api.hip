@@ -235,7 +235,7 @@ struct ace_solver {
     int kernel = ACE_KERNEL_AUTO;
     int depth = 0;
     int zchunk = 32;  // planes per workgroup of the 3D temporal-blocking kernel (0: persistent)
-    int depth2 = 4;   // steps per launch of the 2D temporal-blocking kernel
+    int depth2 = 5;   // steps per launch of the 2D temporal-blocking kernel (fastest on 1024^2)
     int tuned_kernel = 0;  // autotuned choice for ACE_KERNEL_AUTO (0: none)
     // reverse mode
     double *ckpt = nullptr;
@@ -827,6 +827,11 @@ int64_t ace_step_count(const ace_solver *s) { return s ? s->steps : -1; }
 
 const double *ace_field_ptr(const ace_solver *s) { return s ? s->buf[s->cur] : nullptr; }
 
+// Shortest timed trial of the autotuner, and the most steps a lengthened
+// trial may take.
+constexpr double kMinTrialMs = 2.0;
+constexpr int64_t kMaxTrialSteps = 1 << 20;
+
 int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap)
 {
     if (!s || trial_steps < 1) return ACE_E_ARG;
@@ -841,7 +846,7 @@ int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap)
         for (int zc : {0, 16, 24, 32, 40, 48, 64, 128})  // 0: persistent grid
             if (zc <= std::max<int64_t>(s->shape.M0, 16)) cands.push_back({ACE_KERNEL_TBLOCK, zc, s->depth2});
     if (s->p.d == 2 && tblock2d_supported(s->shape))
-        for (int k2 : {1, 2, 4, 6, 8, 12})
+        for (int k2 : {1, 2, 3, 4, 5, 6, 8, 10, 12})
             if (k2 <= tblock2d_max_depth()) cands.push_back({ACE_KERNEL_TBLOCK, s->zchunk, k2});
     const int64_t total = s->p.total;
     double *save = nullptr;
@@ -859,6 +864,16 @@ int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (rc >= 0) rc = hip_status(hipEventCreate(&e0));
     if (rc >= 0) rc = hip_status(hipEventCreate(&e1));
+    // restores the field, then times `n` steps on the handle's stream
+    auto time_run = [&](int64_t n, float *out) -> int {
+        int r;
+        if ((r = restore()) < 0) return r;
+        if ((r = hip_status(hipEventRecord(e0, s->stream))) < 0) return r;
+        if ((r = advance(s, n)) < 0) return r;
+        if ((r = hip_status(hipEventRecord(e1, s->stream))) < 0) return r;
+        if ((r = hip_status(hipEventSynchronize(e1))) < 0) return r;
+        return hip_status(hipEventElapsedTime(out, e0, e1));
+    };
     std::string rec = "{\"kind\": \"solver\", \"trial_steps\": " + std::to_string(trial_steps) +
                       ", \"candidates\": [";
     double best_ms = 1e300;
@@ -869,20 +884,26 @@ int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap)
         s->kernel = c.kernel;
         s->zchunk = c.zchunk;
         s->depth2 = c.depth2;
-        if ((rc = restore()) < 0) break;
-        if ((rc = advance(s, 2)) < 0) break;  // warm-up (loads the code object)
-        if ((rc = restore()) < 0) break;
-        if ((rc = hip_status(hipEventRecord(e0, s->stream))) < 0) break;
-        if ((rc = advance(s, trial_steps)) < 0) break;
-        if ((rc = hip_status(hipEventRecord(e1, s->stream))) < 0) break;
-        if ((rc = hip_status(hipEventSynchronize(e1))) < 0) break;
+        // Each length is run once untimed (code object load, graph capture)
+        // and then timed.  A trial shorter than kMinTrialMs is lengthened to
+        // about that, so small fields are timed in the steady state of a long
+        // run (graph replay) rather than on a few directly issued launches.
+        int64_t steps = trial_steps;
         float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        const double per = ms / (double)trial_steps;
-        char buf[200];
+        if ((rc = time_run(steps, &ms)) < 0) break;
+        if ((rc = time_run(steps, &ms)) < 0) break;
+        if (ms < kMinTrialMs && steps < kMaxTrialSteps) {
+            const double scale = kMinTrialMs / std::max<double>(ms, 1e-3);
+            steps = std::min<int64_t>(kMaxTrialSteps, (int64_t)ceil((double)steps * scale));
+            if ((rc = time_run(steps, &ms)) < 0) break;
+            if ((rc = time_run(steps, &ms)) < 0) break;
+        }
+        const double per = ms / (double)steps;
+        char buf[240];
         snprintf(buf, sizeof buf,
-                 "%s{\"kernel\": %d, \"zchunk\": %d, \"depth2\": %d, \"ms_per_step\": %.6f}",
-                 first ? "" : ", ", c.kernel, c.zchunk, c.depth2, per);
+                 "%s{\"kernel\": %d, \"zchunk\": %d, \"depth2\": %d, \"steps\": %lld, "
+                 "\"ms_per_step\": %.6f}",
+                 first ? "" : ", ", c.kernel, c.zchunk, c.depth2, (long long)steps, per);
         rec += buf;
         first = false;
         if (per < best_ms) {

@@ -282,8 +282,11 @@ __global__ __launch_bounds__(T::UNT) void k_pop_update(Shape s, PopCoef c, const
         for (int r = 0; r < URYT; ++r) {
             if (!ok[r]) continue;
             const int64_t o = z * PS + oidx[r];
+            // the new populations are not read again by this launch:
+            // streaming (non-temporal) stores keep them out of the way of the
+            // inputs in L2
 #pragma unroll
-            for (int k = 0; k < Q; ++k) fout[k * c.ps + o] = outv[r][k];
+            for (int k = 0; k < Q; ++k) __builtin_nontemporal_store(outv[r][k], fout + k * c.ps + o);
         }
     };
 

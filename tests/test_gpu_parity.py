@@ -4,6 +4,7 @@ Tolerances: one step within a few ulp (the GPU evaluates the explicit part
 with FMAs and solves the cubic to ~1 ulp, the oracle rounds the exact root);
 the full workloads within 1e-12 absolute in phi and 1e-12 relative in the
 energy, the bar the method's parity is held to."""
+import json
 import math
 
 import numpy as np
@@ -128,6 +129,41 @@ def test_standalone_monitor_on_tile_edges(ace, orc, bc, M):
     s.set_phi0(phi)
     assert s.energy() == pytest.approx(p.energy(phi), rel=1e-14)
     assert s.maxnorm() == p.maxnorm(phi)
+
+
+@pytest.mark.parametrize("d,N,bc", [(1, (300,), 1), (2, (61, 130), 0), (3, (21, 35, 70), 2)])
+def test_autotune_restores_the_field_and_keeps_results(ace, orc, d, N, bc, tmp_path, monkeypatch):
+    """ace_autotune times every candidate from the current field and then
+    restores it (field and step count); its choice is one of the timed
+    candidates, computes the oracle's field, and is written to the tune cache,
+    from which a new handle of the same problem takes it."""
+    monkeypatch.setenv("ACE_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    dx = 1.0 / 64
+    dt = 1e-3
+    eps = math.sqrt(0.1 * dx * dx / dt)
+    args = (d, list(N), [0.0] * d, [n * dx for n in N], eps, dt, bc)
+    s = ace.Solver(*args)
+    p = orc.Problem(*args)
+    phi0 = np.random.default_rng(5 + d).uniform(-1, 1, p.shape)
+    s.set_phi0(phi0)
+    s.step(3)
+    before = s.get_phi()
+    rec = json.loads(s.autotune(5))
+    assert np.array_equal(s.get_phi(), before) and s.step_count == 3
+    cands = [(c["kernel"], c["zchunk"], c["depth2"]) for c in rec["candidates"]]
+    ch = rec["choice"]
+    assert (ch["kernel"], ch["zchunk"], ch["depth2"]) in cands
+    assert all(c["ms_per_step"] > 0 and c["steps"] >= 5 for c in rec["candidates"])
+    if d == 2:
+        depths = {c["depth2"] for c in rec["candidates"] if c["kernel"] == ace.ACE_KERNEL_TBLOCK}
+        assert depths >= {1, 2, 3, 4, 5, 6, 8}
+    s.step(20)
+    want, _, _ = p.run(phi0, 23)
+    np.testing.assert_allclose(s.get_phi(), want, rtol=0, atol=1e-13)
+    t = ace.Solver(*args)
+    assert t.get_kernel() == s.get_kernel()
+    t.close()
+    s.close()
 
 
 def test_edge_cases(ace, orc):
