@@ -91,14 +91,30 @@ def cpu_baseline(w, phi0_full, min_seconds=10.0):
     return out
 
 
+# Depth of the 2D blocked kernel for the adjoint workload.  On 512^2 with
+# 32-step checkpoint segments, depths 1..12 give forward / backward (ms):
+# 1: 5.31 / 8.77, 2: 3.11 / 6.02, 3: 2.47 / 5.11, 4: 2.00 / 4.52,
+# 5: 1.79 / 4.22, 6: 2.08 / 4.31, 8: 1.73 / 3.54, 10: 2.04 / 5.43,
+# 12: 2.10 / 5.98.  Depth 8 is the fastest for both halves: its 16 x 48 tiles
+# make 352 workgroups (240 at depth 5, fewer than the 256 CUs) and it divides
+# the segments evenly.  The forward-step autotuner cannot see the reverse
+# sweep and picks 5 or 8 (1.79 vs 1.73 ms).
+ADJOINT_DEPTH = 8
+
+
 def adjoint_ratio(ace, torch):
     """Backward / forward wall time: 2D Neumann 512^2, 1000 steps, checkpoints
-    every 32 (forward = ace_forward_ckpt, backward = ace_backward)."""
+    every 32 (forward = ace_forward_ckpt, backward = ace_backward), with the 2D
+    blocked kernel at ADJOINT_DEPTH steps per launch in the forward, the
+    recompute and the reverse sweep."""
     from paper_2312_07010_amd import inputs
     w = inputs.WADJ
     s = ace.Solver(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
     s.use_torch_stream()
+    s.set_kernel(ace.ACE_KERNEL_TBLOCK, ADJOINT_DEPTH)
     phi0 = torch.tensor(inputs.uniform_field(s.shape, w.lo, w.hi, w.seed), device="cuda")
+    k, per = s.get_kernel()
+    kernel = f"{kernel_name(ace, w.d, k)} ({per} step(s) per launch)"
     tgt = torch.tensor(inputs.uniform_field(s.shape, w.lo, w.hi, w.extra["target_seed"]),
                        device="cuda")
     s.forward_ckpt(phi0, w.steps, w.extra["ckpt_every"])  # warm-up, same sizes
@@ -120,7 +136,7 @@ def adjoint_ratio(ace, torch):
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     s.close()
-    return (t3 - t2) / (t1 - t0), (t1 - t0) * 1e3, (t3 - t2) * 1e3
+    return (t3 - t2) / (t1 - t0), (t1 - t0) * 1e3, (t3 - t2) * 1e3, kernel
 
 
 def batched_speedup(ace, torch):
@@ -465,9 +481,9 @@ def main():
                 out["population_rlb"] = {"error": repr(e)}
             torch.cuda.empty_cache()
         try:
-            ratio, fwd_ms, bwd_ms = adjoint_ratio(ace, torch)
+            ratio, fwd_ms, bwd_ms, adj_kernel = adjoint_ratio(ace, torch)
             out["adjoint_cost_ratio"] = ratio
-            out["adjoint_ms"] = {"forward": fwd_ms, "backward": bwd_ms}
+            out["adjoint_ms"] = {"forward": fwd_ms, "backward": bwd_ms, "kernel": adj_kernel}
         except Exception as e:  # report, never hide
             out["adjoint_cost_ratio"] = None
             out["adjoint_error"] = repr(e)

@@ -104,13 +104,21 @@ def test_adjoint_full_workload_512(ace, orc):
     phiT, _, _ = p.run(phi0, w.steps)
     lam = phiT - target
     g_or, _, ge_or = p.adjoint(phi0, w.steps, lam)
-    g, ge = s.adjoint(phi0, w.steps, w.extra["ckpt_every"], lam)
-    np.testing.assert_allclose(s.get_phi(), phiT, rtol=0, atol=1e-12)
     scale = np.abs(g_or).max()
-    err = np.abs(g - g_or).max() / scale
-    print(f"max |dphi0 - oracle| / max|oracle| = {err:.3e}; d/deps2 {ge:.12e} vs {ge_or:.12e}")
-    assert err <= 1e-10
-    assert ge == pytest.approx(ge_or, rel=1e-10)
+    grads = []
+    # the default kernel choice, and the 2D blocked kernel at depth 8 (the
+    # benchmark's launch configuration for this workload)
+    for depth in (0, 8):
+        s.set_kernel(ace.ACE_KERNEL_TBLOCK if depth else ace.ACE_KERNEL_AUTO, depth)
+        g, ge = s.adjoint(phi0, w.steps, w.extra["ckpt_every"], lam)
+        np.testing.assert_allclose(s.get_phi(), phiT, rtol=0, atol=1e-12)
+        err = np.abs(g - g_or).max() / scale
+        print(f"depth {depth}: max |dphi0 - oracle| / max|oracle| = {err:.3e}; "
+              f"d/deps2 {ge:.12e} vs {ge_or:.12e}")
+        assert err <= 1e-10
+        assert ge == pytest.approx(ge_or, rel=1e-10)
+        grads.append(g)
+    assert np.array_equal(grads[0], grads[1])
 
 
 def test_autograd_function(ace, orc):
