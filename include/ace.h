@@ -352,7 +352,10 @@ int ace_batch_autotune(ace_batch *b, int64_t trial_steps, char *json, size_t cap
 /* Times each kernel choice on the handle's problem for trial_steps steps
  * from the current field: the one-thread-per-node, LDS-resident (small
  * fields) and marching kernels, the 3D blocked kernel at several plane chunks
- * and as a persistent grid, and the 2D blocked kernel at several depths.
+ * and as a persistent grid, and the 2D blocked kernel at depths 1..12.  Each
+ * trial is run once untimed and then timed; a trial shorter than 2 ms is
+ * lengthened to about 2 ms (at most 2^20 steps), so that small fields are
+ * timed in the steady state of a long run.  The trials time ace_step only.
  * Keeps the fastest as the ACE_KERNEL_AUTO choice, restores the field, and
  * writes a one-line JSON record of the timings into json (capacity cap
  * bytes, may be NULL).  If the environment variable ACE_AUTOTUNE_CACHE names
