@@ -352,7 +352,7 @@ int ace_batch_autotune(ace_batch *b, int64_t trial_steps, char *json, size_t cap
 /* Times each kernel choice on the handle's problem for trial_steps steps
  * from the current field: the one-thread-per-node, LDS-resident (small
  * fields) and marching kernels, the 3D blocked kernel at several plane chunks
- * and as a persistent grid, and the 2D blocked kernel at depths 1..12.  Each
+ * and as a persistent grid, and the 2D blocked kernel at depths 1-6, 8, 10, 12.  Each
  * trial is run once untimed and then timed; a trial shorter than 2 ms is
  * lengthened to about 2 ms (at most 2^20 steps), so that small fields are
  * timed in the steady state of a long run.  The trials time ace_step only.
