@@ -269,7 +269,8 @@ class Solver:
         return self.last_status
 
     def run_monitored(self, nsteps, every):
-        n = int(nsteps) // int(every) + 1
+        # invalid counts go to the library, which rejects them (ACE_E_ARG)
+        n = int(nsteps) // int(every) + 1 if int(every) >= 1 and int(nsteps) >= 0 else 1
         E = np.empty(n)
         mx = np.empty(n)
         rc = lib().ace_run_monitored(self._h, int(nsteps), int(every), E.ctypes.data_as(_P(_dbl)),

@@ -167,3 +167,37 @@ def test_blocked_2d_adjoint_matches_oracle(ace, orc, bc, depth):
     g2, ge2 = s.adjoint(phi0, nsteps, 11, phiT - target)
     assert np.array_equal(g, g2)
     assert ge2 == pytest.approx(ge, rel=1e-13)
+
+
+def test_adjoint_state_errors(ace, orc):
+    """ace_backward needs checkpoints of the current field: none yet, or a
+    field changed since ace_forward_ckpt (a step, a new phi0), is
+    ACE_E_STATE; a checkpoint interval below 1 is ACE_E_ARG.  A later valid
+    pair still matches the oracle."""
+    s, p = _problem(ace, orc, 2, 20, 0)
+    rng = np.random.default_rng(3)
+    phi0 = rng.uniform(-0.5, 0.5, p.shape)
+    lam = rng.uniform(-0.5, 0.5, p.shape)
+    ACE_E_ARG, ACE_E_STATE = -1, -8
+    with pytest.raises(ace.AceError) as e:
+        s.backward(lam)
+    assert e.value.code == ACE_E_STATE
+    with pytest.raises(ace.AceError) as e:
+        s.forward_ckpt(phi0, 10, 0)
+    assert e.value.code == ACE_E_ARG
+    s.forward_ckpt(phi0, 10, 4)
+    s.step(1)
+    with pytest.raises(ace.AceError) as e:
+        s.backward(lam)
+    assert e.value.code == ACE_E_STATE
+    s.forward_ckpt(phi0, 10, 4)
+    s.set_phi0(phi0)
+    with pytest.raises(ace.AceError) as e:
+        s.backward(lam)
+    assert e.value.code == ACE_E_STATE
+    s.forward_ckpt(phi0, 10, 4)
+    g, ge = s.backward(lam)
+    g_or, _, ge_or = p.adjoint(phi0, 10, lam)
+    np.testing.assert_allclose(g, g_or, rtol=0, atol=1e-13 * np.abs(g_or).max())
+    assert ge == pytest.approx(ge_or, rel=1e-11)
+    s.close()

@@ -192,6 +192,29 @@ def test_edge_cases(ace, orc):
     assert s.step_count == 0
 
 
+def test_run_time_argument_errors(ace, orc):
+    """Negative step counts, a monitor cadence below 1, unknown kernels and
+    depths outside a kernel's range are ACE_E_ARG and leave the handle
+    usable."""
+    ACE_E_ARG = -1
+    s3, p3 = _pair(ace, orc, 3, 12, 2)
+    s2, p2 = _pair(ace, orc, 2, 40, 0)
+    calls = [lambda: s3.step(-1), lambda: s3.run_monitored(10, 0),
+             lambda: s3.set_kernel(ace.ACE_KERNEL_TBLOCK, 3),
+             lambda: s3.set_kernel(9), lambda: s3.set_kernel(ace.ACE_KERNEL_DIRECT, -1),
+             lambda: s2.set_kernel(ace.ACE_KERNEL_TBLOCK, 13), lambda: s2.set_plane_chunk(32)]
+    for call in calls:
+        with pytest.raises(ace.AceError) as e:
+            call()
+        assert e.value.code == ACE_E_ARG
+    for s, p in ((s3, p3), (s2, p2)):
+        phi0 = np.random.default_rng(11).uniform(-1, 1, p.shape)
+        s.set_phi0(phi0)
+        s.step(4)
+        np.testing.assert_allclose(s.get_phi(), p.run(phi0, 4)[0], rtol=0, atol=1e-14)
+        s.close()
+
+
 def test_condition_violation_negative_control(ace, orc):
     """kappa = 0.8209 at dt = 1/5 (Sec. 4.1.1): |xi| > 1 occurs, the guarded
     Newton loop still matches the oracle and the max-norm leaves [-1, 1]."""
