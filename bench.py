@@ -183,7 +183,7 @@ def batched_speedup(ace, torch):
     return {"speedup": t_loop / t_batch, "batched_s": t_batch, "looped_s": t_loop,
             "batched_updates_per_s": updates / t_batch,
             "algorithmic_hbm_frac": BYTES_PER_UPDATE * updates / t_batch / HBM_PEAK,
-            "resident_limit": tune["choice"]["resident_limit"]}
+            "resident_limit": tune["choice"]["resident_limit"], "depth": tune["choice"]["depth"]}
 
 
 WORKLOAD_DESC = {

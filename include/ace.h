@@ -342,9 +342,16 @@ int ace_batch_get_all(ace_batch *b, double *out_all, int where);
  * (limit is capped at the LDS capacity, 8000 doubles); larger ones stream
  * through their two arena slots.  Results do not depend on the choice. */
 int ace_batch_set_resident_limit(ace_batch *b, int64_t limit);
-/* Times one batch step of trial_steps steps for several resident limits on
- * the current fields (which are restored), keeps the fastest, and writes a
- * JSON record of the timings into json (capacity cap, may be NULL). */
+/* Steps per round (temporal-blocking depth, 1..8, default 4) of the 2D
+ * instances too large for LDS, which advance over 32 x 64 LDS regions with a
+ * ring of `depth` nodes recomputed.  Results do not depend on the choice.
+ * Error: ACE_E_ARG outside 1..8. */
+int ace_batch_set_depth(ace_batch *b, int depth);
+/* Times one batch step of trial_steps steps on the current fields (which are
+ * restored): first for depths 2..6 at the current resident limit, then for
+ * several resident limits at the fastest depth.  Keeps the fastest pair and
+ * writes a JSON record of the timings into json (capacity cap, may be
+ * NULL). */
 int ace_batch_autotune(ace_batch *b, int64_t trial_steps, char *json, size_t cap);
 
 /* ---- autotuner ------------------------------------------------------------ */

@@ -99,6 +99,7 @@ _SIGS = {
     "ace_batch_get_phi": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int]),
     "ace_batch_get_all": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
     "ace_batch_set_resident_limit": (ctypes.c_int, [_vp, _i64]),
+    "ace_batch_set_depth": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ace_batch_autotune": (ctypes.c_int, [_vp, _i64, ctypes.c_char_p, ctypes.c_size_t]),
     "ace_autotune": (ctypes.c_int, [_vp, _i64, ctypes.c_char_p, ctypes.c_size_t]),
     "ace_pop_create": (ctypes.c_int, [ctypes.c_int, _P(_i64), _P(_dbl), _P(_dbl), _dbl, _dbl,
@@ -444,6 +445,9 @@ class Batch:
 
     def set_resident_limit(self, limit):
         _check(lib().ace_batch_set_resident_limit(self._h, int(limit)), "ace_batch_set_resident_limit")
+
+    def set_depth(self, depth):
+        _check(lib().ace_batch_set_depth(self._h, int(depth)), "ace_batch_set_depth")
 
     def autotune(self, trial_steps=20):
         buf = ctypes.create_string_buffer(4096)

@@ -148,17 +148,18 @@ __device__ void batch_stream(const BatchInst &I, double *__restrict__ fa, double
     }
 }
 
-// 2D instance too large for LDS, advanced in rounds of up to kTK steps: each
-// round walks the instance's 32 x 64 regions (ring of K nodes), advances each
-// region K levels in LDS (the two padded planes live in the workgroup's LDS
-// array) and writes its tile interior to the other arena slot; a workgroup
-// barrier (with its memory fence) separates the rounds.  The arithmetic and
-// neighbour order are those of the single-instance kernels.
-constexpr int kTK = 4;
+// 2D instance too large for LDS, advanced in rounds of up to tk steps (the
+// batch's depth, 1..kMaxDepth): each round walks the instance's 32 x 64
+// regions (ring of K nodes), advances each region K levels in LDS (the two
+// padded planes live in the workgroup's LDS array) and writes its tile
+// interior to the other arena slot; a workgroup barrier (with its memory
+// fence) separates the rounds.  The arithmetic and neighbour order are those
+// of the single-instance kernels.
+constexpr int kMaxDepth = 8;
 
 template <int BC>
 __device__ void batch_tiles2d(const BatchInst &I, double *__restrict__ fa, double *__restrict__ fb,
-                              int64_t nsteps, double *lds)
+                              int64_t nsteps, double *lds, int tk)
 {
     using namespace tile2d;
     constexpr int TR = kBT / BX;  // thread rows
@@ -177,7 +178,7 @@ __device__ void batch_tiles2d(const BatchInst &I, double *__restrict__ fa, doubl
     int64_t done = 0;
     int par = 0;  // 0: the field is in fa
     while (done < nsteps) {
-        const int K = (int)std::min<int64_t>(kTK, nsteps - done);
+        const int K = (int)std::min<int64_t>(tk, nsteps - done);
         const double *__restrict__ in = par ? fb : fa;
         double *__restrict__ out = par ? fa : fb;
         const int64_t tiles_x = (s.M2 + BX - 2 * K - 1) / (BX - 2 * K);
@@ -243,7 +244,7 @@ __global__ void k_batch_reset(int *counter)
 __global__ __launch_bounds__(kBT) void k_batch(const BatchInst *__restrict__ inst,
                                                const int *__restrict__ order, int ntasks,
                                                int *__restrict__ counter, double *__restrict__ arena_a,
-                                               double *__restrict__ arena_b, int64_t nsteps)
+                                               double *__restrict__ arena_b, int64_t nsteps, int tk)
 {
     __shared__ double f[RESIDENT_MAX + 1];
     __shared__ int task;
@@ -271,9 +272,9 @@ __global__ __launch_bounds__(kBT) void k_batch(const BatchInst *__restrict__ ins
             else if (I.bc == BC_HD) batch_stream<1, BC_HD>(I, fa, fb, nsteps);
             else batch_stream<1, BC_P>(I, fa, fb, nsteps);
         } else {
-            if (I.bc == BC_HN) batch_tiles2d<BC_HN>(I, fa, fb, nsteps, f);
-            else if (I.bc == BC_HD) batch_tiles2d<BC_HD>(I, fa, fb, nsteps, f);
-            else batch_tiles2d<BC_P>(I, fa, fb, nsteps, f);
+            if (I.bc == BC_HN) batch_tiles2d<BC_HN>(I, fa, fb, nsteps, f, tk);
+            else if (I.bc == BC_HD) batch_tiles2d<BC_HD>(I, fa, fb, nsteps, f, tk);
+            else batch_tiles2d<BC_P>(I, fa, fb, nsteps, f, tk);
         }
     }
 }
@@ -322,6 +323,7 @@ struct ace_batch {
     std::vector<int> order;
     int64_t arena_total = 0;
     int64_t resident_limit = RESIDENT_MAX;  // tuned: largest field stepped in LDS
+    int depth = 4;  // tuned: steps per round of the 2D instances stepped over LDS regions
     int device = 0;
     hipStream_t stream = nullptr;   // caller's stream (graph launches go here)
     hipStream_t capture = nullptr;  // private stream used only for graph capture
@@ -383,7 +385,7 @@ int get_graph(ace_batch *b, int64_t nsteps, hipGraphExec_t *out)
     BT_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, b->capture, b->counter);
     hipLaunchKernelGGL(k_batch, dim3(b->grid), dim3(kBT), 0, b->capture, b->inst, b->order_dev,
-                       b->count, b->counter, b->arena_a, b->arena_b, nsteps);
+                       b->count, b->counter, b->arena_a, b->arena_b, nsteps, b->depth);
     hipError_t le = hipGetLastError();
     hipError_t ce = hipStreamEndCapture(b->capture, &g);
     BT_HIP(le);
@@ -588,6 +590,16 @@ int ace_batch_set_resident_limit(ace_batch *b, int64_t limit)
     return upload_tasks(b);
 }
 
+int ace_batch_set_depth(ace_batch *b, int depth)
+{
+    if (!b || depth < 1 || depth > kMaxDepth) return ACE_E_ARG;
+    if (depth != b->depth) {
+        b->depth = depth;
+        drop_graphs(b);  // the captured launches carry the old depth
+    }
+    return ACE_OK;
+}
+
 int ace_batch_autotune(ace_batch *b, int64_t trial_steps, char *json, size_t cap)
 {
     if (!b || trial_steps < 1) return ACE_E_ARG;
@@ -600,45 +612,72 @@ int ace_batch_autotune(ace_batch *b, int64_t trial_steps, char *json, size_t cap
     };
     int rc = hip_status(hipMemcpyAsync(save, b->arena_a, sizeof(double) * b->arena_total,
                                        hipMemcpyDeviceToDevice, b->stream));
+    // First the depth of the region rounds at the current resident limit,
+    // then the resident limit at the chosen depth.
+    const int depths[] = {2, 3, 4, 5, 6};
     const int64_t limits[] = {0, 1024, 2048, 4096, RESIDENT_MAX};
     double best_ms = 1e300;
-    int64_t best = b->resident_limit;
+    int64_t best_lim = b->resident_limit;
+    int best_depth = b->depth;
     std::string rec = "{\"kind\": \"batch\", \"trial_steps\": " + std::to_string(trial_steps) +
                       ", \"candidates\": [";
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (rc >= 0) rc = hip_status(hipEventCreate(&e0));
     if (rc >= 0) rc = hip_status(hipEventCreate(&e1));
     bool first = true;
-    for (int64_t lim : limits) {
-        if (rc < 0) break;
-        if ((rc = ace_batch_set_resident_limit(b, lim)) < 0) break;
-        if ((rc = restore()) < 0) break;
-        if ((rc = ace_batch_step(b, trial_steps)) < 0) break;  // builds the graph, warms up
-        if ((rc = restore()) < 0) break;
-        if ((rc = hip_status(hipEventRecord(e0, b->stream))) < 0) break;
-        if ((rc = ace_batch_step(b, trial_steps)) < 0) break;
-        if ((rc = hip_status(hipEventRecord(e1, b->stream))) < 0) break;
-        if ((rc = hip_status(hipEventSynchronize(e1))) < 0) break;
+    // times one batch step of trial_steps for (lim, depth); returns ms or a negative error
+    auto trial = [&](int64_t lim, int depth, double *ms_out) -> int {
+        int r;
+        if ((r = ace_batch_set_resident_limit(b, lim)) < 0) return r;
+        if ((r = ace_batch_set_depth(b, depth)) < 0) return r;
+        if ((r = restore()) < 0) return r;
+        if ((r = ace_batch_step(b, trial_steps)) < 0) return r;  // builds the graph, warms up
+        if ((r = restore()) < 0) return r;
+        if ((r = hip_status(hipEventRecord(e0, b->stream))) < 0) return r;
+        if ((r = ace_batch_step(b, trial_steps)) < 0) return r;
+        if ((r = hip_status(hipEventRecord(e1, b->stream))) < 0) return r;
+        if ((r = hip_status(hipEventSynchronize(e1))) < 0) return r;
         float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
+        if ((r = hip_status(hipEventElapsedTime(&ms, e0, e1))) < 0) return r;
+        *ms_out = ms;
         char buf[160];
-        snprintf(buf, sizeof buf, "%s{\"resident_limit\": %lld, \"ms\": %.4f}", first ? "" : ", ",
-                 (long long)lim, ms);
+        snprintf(buf, sizeof buf, "%s{\"resident_limit\": %lld, \"depth\": %d, \"ms\": %.4f}",
+                 first ? "" : ", ", (long long)lim, depth, ms);
         rec += buf;
         first = false;
+        return ACE_OK;
+    };
+    const int64_t lim0 = b->resident_limit;
+    for (int depth : depths) {
+        if (rc < 0) break;
+        double ms = 0.0;
+        if ((rc = trial(lim0, depth, &ms)) < 0) break;
         if (ms < best_ms) {
             best_ms = ms;
-            best = lim;
+            best_depth = depth;
+            best_lim = lim0;
+        }
+    }
+    for (int64_t lim : limits) {
+        if (rc < 0) break;
+        if (lim == lim0) continue;  // timed above at the chosen depth
+        double ms = 0.0;
+        if ((rc = trial(lim, best_depth, &ms)) < 0) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_lim = lim;
         }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    if (rc >= 0) rc = ace_batch_set_resident_limit(b, best);
+    if (rc >= 0) rc = ace_batch_set_resident_limit(b, best_lim);
+    if (rc >= 0) rc = ace_batch_set_depth(b, best_depth);
     if (rc >= 0) rc = restore();
     if (rc >= 0) rc = hip_status(hipStreamSynchronize(b->stream));
     (void)hipFree(save);
     if (rc < 0) return rc;
-    rec += "], \"choice\": {\"resident_limit\": " + std::to_string(best) + "}}";
+    rec += "], \"choice\": {\"resident_limit\": " + std::to_string(best_lim) +
+           ", \"depth\": " + std::to_string(best_depth) + "}}";
     if (json && cap > 0) snprintf(json, cap, "%s", rec.c_str());
     return ACE_OK;
 }

@@ -1,4 +1,5 @@
 """Batched persistent launch vs the oracle and vs single-instance ace_step."""
+import json
 import math
 
 import numpy as np
@@ -80,6 +81,38 @@ def test_resident_limit_does_not_change_results(ace):
     b.set_all(phi0)
     b.step(17)
     for x, y in zip(b.get_all(), outs[0]):
+        assert np.array_equal(x, y)
+
+
+def test_region_depth_does_not_change_results(ace):
+    """The steps per round of the 2D instances stepped over LDS regions
+    (1..8; 17 steps end on a short round for most depths) leave every
+    instance bit for bit unchanged; 0 and 9 are rejected; the autotuner picks
+    a depth and a resident limit."""
+    insts = _mixed(1)
+    b = ace.Batch(insts)
+    rng = np.random.default_rng(10)
+    phi0 = [rng.uniform(-0.9, 0.9, shp) for shp in b.shapes]
+    ref = None
+    for depth in (4, 1, 2, 3, 5, 6, 8):
+        b.set_depth(depth)
+        b.set_all(phi0)
+        b.step(17)
+        got = b.get_all()
+        if ref is None:
+            ref = got
+        for x, y in zip(got, ref):
+            assert np.array_equal(x, y), depth
+    for bad in (0, 9):
+        with pytest.raises(ace.AceError) as e:
+            b.set_depth(bad)
+        assert e.value.code == -1
+    rec = json.loads(b.autotune(5))
+    assert rec["choice"]["depth"] in (2, 3, 4, 5, 6)
+    assert {c["depth"] for c in rec["candidates"]} == {2, 3, 4, 5, 6}
+    b.set_all(phi0)
+    b.step(17)
+    for x, y in zip(b.get_all(), ref):
         assert np.array_equal(x, y)
 
 
