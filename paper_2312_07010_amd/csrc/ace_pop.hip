@@ -138,9 +138,9 @@ constexpr int VMCNT0 = 0x0F70;
 // k_pop_moment) or straight from the populations (fused).  A workgroup owns
 // a UOY x UX output tile aligned to whole cache lines (each wavefront stores
 // 64 consecutive doubles of every population array; each thread URYT rows of
-// one column); phi of the tile plus its one-node ring sits in LDS, the ring
-// loaded by threads 0..URING-1 with one extra load each (the other threads
-// load their own node again, so every load is unconditional).  In 3D the
+// one column); phi of the tile plus its one-node ring sits in LDS, ring node
+// h loaded by thread h % UNT (URPT extra loads per thread; a thread past the
+// ring's end loads its own node again, so every load is unconditional).  In 3D the
 // workgroup marches along axis 0 with phi of planes z-1, z, z+1 of its own
 // nodes in registers.  The default tile is 16 x 128 on 512 threads (4 rows
 // per thread): against 16 x 64 it halves the ring columns per node, whose
@@ -156,9 +156,9 @@ struct PopTile {
     static constexpr int ULH = UOY + 2;
     static constexpr int ULP = ULW * ULH;
     static constexpr int UNT = UX * UTR;              // threads
-    static constexpr int URING = 2 * UX + 2 * UOY;    // ring nodes, one per thread
+    static constexpr int URING = 2 * UX + 2 * UOY;    // ring nodes
+    static constexpr int URPT = (URING + UNT - 1) / UNT;  // ring nodes per thread
     static_assert((UX & (UX - 1)) == 0 && UX >= 64, "tile columns: a power of two, whole wavefronts");
-    static_assert(URING <= UNT, "one ring node per thread at most");
 };
 using PopTileDefault = PopTile<128, 4, 4>;  // 16 x 128, 512 threads
 
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(T::UNT) void k_pop_update(Shape s, PopCoef c, const
                                                        int zchunk)
 {
     constexpr int UX = T::UX, URYT = T::URYT, UOY = T::UOY, ULW = T::ULW, ULH = T::ULH,
-                  ULP = T::ULP, URING = T::URING;
+                  ULP = T::ULP, URING = T::URING, URPT = T::URPT, UNT = T::UNT;
     constexpr int Q = 2 * D + 1;
     constexpr int QIN = FUSED ? Q : 1;
     __shared__ double L[2 * ULP];
@@ -200,32 +200,39 @@ __global__ __launch_bounds__(T::UNT) void k_pop_update(Shape s, PopCoef c, const
         ok[r] = xg < s.M2 && yg < s.M1;
         oidx[r] = ok[r] ? yg * s.M2 + xg : 0;
     }
-    // ring slot of this thread (threads >= URING reload their first node)
-    const int h = threadIdx.x;
-    int hslot = -1;
-    int64_t hoff = off[0];
-    bool hz = zr[0];
-    if (h < URING) {
-        int64_t hy, hx;
-        int ly, lxx;
-        if (h < UX) {  // row above
-            hy = y0 - 1; hx = x0 + h; ly = 0; lxx = 1 + h;
-        } else if (h < 2 * UX) {  // row below
-            hy = y0 + UOY; hx = x0 + (h - UX); ly = ULH - 1; lxx = 1 + (h - UX);
-        } else if (h < 2 * UX + UOY) {  // column left
-            hy = y0 + (h - 2 * UX); hx = x0 - 1; ly = 1 + (h - 2 * UX); lxx = 0;
-        } else {  // column right
-            hy = y0 + (h - 2 * UX - UOY); hx = x0 + UX; ly = 1 + (h - 2 * UX - UOY); lxx = ULW - 1;
+    // ring slots of this thread: ring node threadIdx.x + j * UNT for
+    // j < URPT (a thread past the ring's end reloads its own first node)
+    int hslot[URPT];
+    int64_t hoff[URPT];
+    bool hz[URPT];
+#pragma unroll
+    for (int j = 0; j < URPT; ++j) {
+        const int h = threadIdx.x + j * UNT;
+        hslot[j] = -1;
+        hoff[j] = off[0];
+        hz[j] = zr[0];
+        if (h < URING) {
+            int64_t hy, hx;
+            int ly, lxx;
+            if (h < UX) {  // row above
+                hy = y0 - 1; hx = x0 + h; ly = 0; lxx = 1 + h;
+            } else if (h < 2 * UX) {  // row below
+                hy = y0 + UOY; hx = x0 + (h - UX); ly = ULH - 1; lxx = 1 + (h - UX);
+            } else if (h < 2 * UX + UOY) {  // column left
+                hy = y0 + (h - 2 * UX); hx = x0 - 1; ly = 1 + (h - 2 * UX); lxx = 0;
+            } else {  // column right
+                hy = y0 + (h - 2 * UX - UOY); hx = x0 + UX; ly = 1 + (h - 2 * UX - UOY); lxx = ULW - 1;
+            }
+            bool z1 = false, z2 = false;
+            const int64_t my = pmap<BC>(hy, s.M1, z1);
+            const int64_t mxx = pmap<BC>(hx, s.M2, z2);
+            hoff[j] = my * s.M2 + mxx;
+            hz[j] = z1 || z2;
+            hslot[j] = ly * ULW + lxx;
         }
-        bool z1 = false, z2 = false;
-        const int64_t my = pmap<BC>(hy, s.M1, z1);
-        const int64_t mxx = pmap<BC>(hx, s.M2, z2);
-        hoff = my * s.M2 + mxx;
-        hz = z1 || z2;
-        hslot = ly * ULW + lxx;
     }
 
-    double own_raw[QIN][URYT], ring_raw[QIN];
+    double own_raw[QIN][URYT], ring_raw[QIN][URPT];
     bool zown = false, zring = false;
     auto issue_own = [&](int64_t zz) {
         zown = false;
@@ -239,7 +246,9 @@ __global__ __launch_bounds__(T::UNT) void k_pop_update(Shape s, PopCoef c, const
         zring = false;
         const int64_t base = pmap<BC>(zz, s.M0, zring) * PS;
 #pragma unroll
-        for (int k = 0; k < QIN; ++k) ring_raw[k] = src[k * c.ps + base + hoff];
+        for (int j = 0; j < URPT; ++j)
+#pragma unroll
+            for (int k = 0; k < QIN; ++k) ring_raw[k][j] = src[k * c.ps + base + hoff[j]];
     };
     auto own_val = [&](int r) {
         double v = own_raw[0][r];
@@ -250,10 +259,13 @@ __global__ __launch_bounds__(T::UNT) void k_pop_update(Shape s, PopCoef c, const
     auto stage = [&](double *Lb, const double (&pc)[URYT]) {
 #pragma unroll
         for (int r = 0; r < URYT; ++r) Lb[(1 + tr * URYT + r) * ULW + 1 + lx] = pc[r];
-        double v = ring_raw[0];
 #pragma unroll
-        for (int k = 1; k < QIN; ++k) v += ring_raw[k];
-        if (hslot >= 0) Lb[hslot] = (zring || hz) ? 0.0 : v;
+        for (int j = 0; j < URPT; ++j) {
+            double v = ring_raw[0][j];
+#pragma unroll
+            for (int k = 1; k < QIN; ++k) v += ring_raw[k][j];
+            if (hslot[j] >= 0) Lb[hslot[j]] = (zring || hz[j]) ? 0.0 : v;
+        }
     };
     double outv[URYT][Q];
     auto update_plane = [&](const double *Lc, const double (&pm)[URYT], const double (&pc)[URYT],
