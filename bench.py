@@ -93,9 +93,9 @@ def cpu_baseline(w, phi0_full, min_seconds=10.0):
 
 # Depth of the 2D blocked kernel for the adjoint workload.  On 512^2 with
 # 32-step checkpoint segments, depths 1..12 give forward / backward (ms):
-# 1: 5.31 / 8.77, 2: 3.11 / 6.02, 3: 2.47 / 5.11, 4: 2.00 / 4.52,
-# 5: 1.79 / 4.22, 6: 2.08 / 4.31, 8: 1.73 / 3.54, 10: 2.04 / 5.43,
-# 12: 2.10 / 5.98.  Depth 8 is the fastest for both halves: its 16 x 48 tiles
+# 1: 5.41 / 8.67, 2: 3.12 / 5.54, 3: 2.46 / 4.14, 4: 2.02 / 3.44,
+# 5: 1.79 / 3.17, 6: 2.09 / 3.36, 8: 1.74 / 3.10, 10: 2.02 / 4.05,
+# 12: 2.08 / 4.63.  Depth 8 is the fastest for both halves: its 16 x 48 tiles
 # make 352 workgroups (240 at depth 5, fewer than the 256 CUs) and it divides
 # the segments evenly.  The forward-step autotuner cannot see the reverse
 # sweep and picks 5 or 8 (1.79 vs 1.73 ms).

@@ -148,6 +148,14 @@ __global__ __launch_bounds__(BNT) void k_adjoint_tb2d(Shape s, StepCoef c,
         P[BLP + (ry + 1) * BLW + tx + 1] = (goffs[j] < 0) ? 0.0 : states[(int64_t)K * stride + goffs[j]];
     }
     const bool xin = g.xg >= 0 && g.xg < s.M2 && tx >= K && tx < BX - K;
+    // the stored state of the next level down is loaded into registers one
+    // level ahead, so its latency overlaps the current level
+    double nxt[BRT];
+    auto fetch = [&](int i) {
+#pragma unroll
+        for (int j = 0; j < BRT; ++j) nxt[j] = (goffs[j] < 0) ? 0.0 : states[(int64_t)i * stride + goffs[j]];
+    };
+    fetch(K - 1);
     double gsum = 0.0;
     int cur1 = 1;  // buffer holding phi_{j+1}
     for (int i = K - 1; i >= 0; --i) {
@@ -158,8 +166,9 @@ __global__ __launch_bounds__(BNT) void k_adjoint_tb2d(Shape s, StepCoef c,
 #pragma unroll
         for (int j = 0; j < BRT; ++j) {
             const int ry = tr + BTR * j;
-            p0[(ry + 1) * BLW + tx + 1] = (goffs[j] < 0) ? 0.0 : states[(int64_t)i * stride + goffs[j]];
+            p0[(ry + 1) * BLW + tx + 1] = nxt[j];
         }
+        if (i > 0) fetch(i - 1);
         // mu of the region rows still exact
 #pragma unroll
         for (int j = 0; j < BRT; ++j) {
