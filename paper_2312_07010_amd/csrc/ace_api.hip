@@ -335,6 +335,8 @@ int launch_steps(ace_solver *s, int kernel, int64_t remaining, bool want_mon, in
 
 void drop_graphs(ace_solver *s)
 {
+    // a replay may still run on the handle's stream
+    if (!s->graphs.empty()) (void)hipStreamSynchronize(s->stream);
     for (auto &g : s->graphs) {
         (void)hipGraphExecDestroy(g.e);
         (void)hipGraphDestroy(g.g);

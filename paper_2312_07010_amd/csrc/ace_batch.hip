@@ -348,6 +348,8 @@ namespace {
 
 void drop_graphs(ace_batch *b)
 {
+    // a replay may still run on the handle's stream
+    if (!b->graphs.empty()) (void)hipStreamSynchronize(b->stream);
     for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
     for (auto &kv : b->graph_defs) (void)hipGraphDestroy(kv.second);
     b->graphs.clear();
@@ -360,6 +362,8 @@ int64_t task_cost(const BatchInst &I) { return I.total * (I.resident ? 1 : 3); }
 
 int upload_tasks(ace_batch *b)
 {
+    // the tables below are read by any launch still running on the stream
+    BT_HIP(hipStreamSynchronize(b->stream));
     for (auto &I : b->host_inst) I.resident = (I.total <= b->resident_limit) ? 1 : 0;
     b->order.resize(b->count);
     std::iota(b->order.begin(), b->order.end(), 0);
