@@ -145,8 +145,11 @@ def _check(code, where):
     return code
 
 
-def _host(a):
+def _host(a, n=None):
+    """Contiguous float64 copy (or view) and its address; n: required size."""
     a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and a.size != n:
+        raise ValueError(f"array has {a.size} elements, {n} expected")
     return a, a.ctypes.data
 
 
@@ -154,10 +157,14 @@ def _is_device(x):
     return hasattr(x, "is_cuda") and x.is_cuda
 
 
-def _dev(t):
+def _dev(t, n=None):
+    """Address of a contiguous float64 device tensor; n: required element
+    count (the library reads or writes exactly that many)."""
     import torch
     if t.dtype != torch.float64 or not t.is_contiguous():
         raise ValueError("device arrays must be contiguous float64 tensors")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"tensor has {t.numel()} elements, {n} expected")
     return t.data_ptr()
 
 
@@ -221,8 +228,8 @@ class Solver:
         self.set_stream(current_stream())
 
     def bind_fields(self, a, b):
-        pa = _dev(a) if a is not None else None
-        pb = _dev(b) if b is not None else None
+        pa = _dev(a, self.total) if a is not None else None
+        pb = _dev(b, self.total) if b is not None else None
         _check(lib().ace_bind_fields(self._h, pa, pb), "ace_bind_fields")
 
     def set_eps(self, eps):
@@ -256,7 +263,7 @@ class Solver:
 
     def set_phi0(self, phi0):
         if _is_device(phi0):
-            rc = lib().ace_set_phi0(self._h, _dev(phi0), ACE_DEVICE)
+            rc = lib().ace_set_phi0(self._h, _dev(phi0, self.total), ACE_DEVICE)
         else:
             a, p = _host(phi0)
             if a.size != self.total:
@@ -301,7 +308,7 @@ class Solver:
 
     def get_phi(self, out=None):
         if out is not None and _is_device(out):
-            _check(lib().ace_get_phi(self._h, _dev(out), ACE_DEVICE), "ace_get_phi")
+            _check(lib().ace_get_phi(self._h, _dev(out, self.total), ACE_DEVICE), "ace_get_phi")
             return out
         a = np.empty(self.shape)
         _check(lib().ace_get_phi(self._h, a.ctypes.data, ACE_HOST), "ace_get_phi")
@@ -317,9 +324,10 @@ class Solver:
     # reverse mode ---------------------------------------------------------
     def forward_ckpt(self, phi0, nsteps, ckpt_every):
         if _is_device(phi0):
-            rc = lib().ace_forward_ckpt(self._h, _dev(phi0), ACE_DEVICE, int(nsteps), int(ckpt_every))
+            rc = lib().ace_forward_ckpt(self._h, _dev(phi0, self.total), ACE_DEVICE, int(nsteps),
+                                        int(ckpt_every))
         else:
-            a, p = _host(phi0)
+            a, p = _host(phi0, self.total)
             rc = lib().ace_forward_ckpt(self._h, p, ACE_HOST, int(nsteps), int(ckpt_every))
         return _check(rc, "ace_forward_ckpt")
 
@@ -328,9 +336,10 @@ class Solver:
         if _is_device(lambdaT):
             import torch
             out = dphi0 if dphi0 is not None else torch.empty_like(lambdaT)
-            rc = lib().ace_backward(self._h, _dev(lambdaT), _dev(out), ctypes.byref(g), ACE_DEVICE)
+            rc = lib().ace_backward(self._h, _dev(lambdaT, self.total), _dev(out, self.total),
+                                    ctypes.byref(g), ACE_DEVICE)
         else:
-            lam, p = _host(lambdaT)
+            lam, p = _host(lambdaT, self.total)
             out = np.empty(self.shape)
             rc = lib().ace_backward(self._h, p, out.ctypes.data, ctypes.byref(g), ACE_HOST)
         _check(rc, "ace_backward")
@@ -338,8 +347,8 @@ class Solver:
 
     def adjoint(self, phi0, nsteps, ckpt_every, lambdaT):
         """Host arrays in, (dL/dphi0, dL/d(eps^2)) out."""
-        a, pa = _host(phi0)
-        lam, pl = _host(lambdaT)
+        a, pa = _host(phi0, self.total)
+        lam, pl = _host(lambdaT, self.total)
         out = np.empty(self.shape)
         g = _dbl()
         rc = lib().ace_adjoint(self._h, pa, int(nsteps), int(ckpt_every), pl, out.ctypes.data,
@@ -507,7 +516,7 @@ class Pop:
 
     def set_phi0(self, phi0):
         if _is_device(phi0):
-            rc = lib().ace_pop_set_phi0(self._h, _dev(phi0), ACE_DEVICE)
+            rc = lib().ace_pop_set_phi0(self._h, _dev(phi0, self.total), ACE_DEVICE)
         else:
             a, p = _host(phi0)
             if a.size != self.total:
@@ -517,7 +526,7 @@ class Pop:
 
     def set_populations(self, f):
         if _is_device(f):
-            return _check(lib().ace_pop_set_populations(self._h, _dev(f), ACE_DEVICE),
+            return _check(lib().ace_pop_set_populations(self._h, _dev(f, self.q * self.total), ACE_DEVICE),
                           "ace_pop_set_populations")
         a, p = _host(f)
         if a.size != self.q * self.total:
@@ -526,7 +535,7 @@ class Pop:
 
     def get_populations(self, out=None):
         if out is not None and _is_device(out):
-            _check(lib().ace_pop_get_populations(self._h, _dev(out), ACE_DEVICE),
+            _check(lib().ace_pop_get_populations(self._h, _dev(out, self.q * self.total), ACE_DEVICE),
                    "ace_pop_get_populations")
             return out
         a = np.empty((self.q,) + self.shape)
@@ -538,7 +547,7 @@ class Pop:
 
     def get_phi(self, out=None):
         if out is not None and _is_device(out):
-            _check(lib().ace_pop_get_phi(self._h, _dev(out), ACE_DEVICE), "ace_pop_get_phi")
+            _check(lib().ace_pop_get_phi(self._h, _dev(out, self.total), ACE_DEVICE), "ace_pop_get_phi")
             return out
         a = np.empty(self.shape)
         _check(lib().ace_pop_get_phi(self._h, a.ctypes.data, ACE_HOST), "ace_pop_get_phi")

@@ -215,6 +215,49 @@ def test_run_time_argument_errors(ace, orc):
         s.close()
 
 
+def test_binding_rejects_wrong_sizes(ace, orc):
+    """The library reads or writes exactly `total` doubles (q * total for the
+    populations) through the pointers it is given, so the binding refuses
+    host arrays and device tensors of any other size before the call."""
+    import torch
+    s, p = _pair(ace, orc, 2, 20, 0)
+    n = s.total
+
+    def dev(k):
+        return torch.zeros(k, dtype=torch.float64, device="cuda")
+
+    for k in (n - 1, n + 1):
+        for call in (lambda: s.set_phi0(dev(k)), lambda: s.get_phi(dev(k)),
+                     lambda: s.forward_ckpt(dev(k), 4, 2), lambda: s.bind_fields(dev(k), dev(n)),
+                     lambda: s.adjoint(np.zeros(k), 4, 2, np.zeros(n)),
+                     lambda: s.adjoint(np.zeros(n), 4, 2, np.zeros(k))):
+            with pytest.raises(ValueError):
+                call()
+    s.forward_ckpt(np.zeros(p.shape), 4, 2)
+    with pytest.raises(ValueError):
+        s.backward(np.zeros(n + 1))
+    with pytest.raises(ValueError):
+        s.backward(dev(n), dev(n - 1))
+    phi0 = np.random.default_rng(2).uniform(-1, 1, p.shape)
+    s.set_phi0(dev(n).copy_(torch.from_numpy(phi0.ravel())))
+    s.step(3)
+    np.testing.assert_allclose(s.get_phi(), p.run(phi0, 3)[0], rtol=0, atol=1e-14)
+    g = ace.Pop(*_args_pop(s))
+    for call in (lambda: g.set_populations(dev(g.q * n - 1)), lambda: g.get_populations(dev(g.q * n + 1)),
+                 lambda: g.get_phi(dev(n - 1)), lambda: g.set_phi0(dev(n + 1))):
+        with pytest.raises(ValueError):
+            call()
+    g.close()
+    s.close()
+
+
+def _args_pop(s):
+    prm = s.params
+    d = prm["d"]
+    N = prm["N"][:d]
+    return (d, N, [0.0] * d, [n * prm["dx"] for n in N], prm["eps"], prm["dt"], prm["bc"])
+
+
 def test_condition_violation_negative_control(ace, orc):
     """kappa = 0.8209 at dt = 1/5 (Sec. 4.1.1): |xi| > 1 occurs, the guarded
     Newton loop still matches the oracle and the max-norm leaves [-1, 1]."""
