@@ -5,12 +5,13 @@
 // start first) and runs every step of that instance before taking another.
 // Instances whose field fits in LDS are stepped entirely in LDS (one global
 // read and one write per launch).  Larger 2D ones advance in rounds of up to
-// four steps over 32 x 64 LDS regions (temporal blocking, one global read and
-// write per round); larger 1D ones ping-pong between their two arena slots
-// with a workgroup barrier between steps.  Every instance carries
-// its own shape, boundary condition, kappa, h and Newton count, and every
-// update uses the same arithmetic as the single-instance kernels, so each
-// instance's result equals ace_step on that instance bit for bit.
+// `depth` steps (1..8, autotuned; 4 by default) over 32 x 64 LDS regions
+// (temporal blocking, one global read and write per round); larger 1D ones
+// ping-pong between their two arena slots with a workgroup barrier between
+// steps.  Every instance carries its own shape, boundary condition, kappa, h
+// and Newton count, and every update uses the same arithmetic as the
+// single-instance kernels, so each instance's result equals ace_step on that
+// instance bit for bit.
 //
 // The launch pair (counter reset by a one-thread kernel, then the persistent
 // kernel) is captured once per step count into a HIP graph and replayed.
