@@ -201,3 +201,35 @@ def test_adjoint_state_errors(ace, orc):
     np.testing.assert_allclose(g, g_or, rtol=0, atol=1e-13 * np.abs(g_or).max())
     assert ge == pytest.approx(ge_or, rel=1e-11)
     s.close()
+
+
+@pytest.mark.parametrize("d,bc,N", [(1, 2, 40), (2, 0, 24), (2, 1, 23), (3, 2, 10)])
+def test_dot_product_against_torch_tangent(ace, orc, d, bc, N):
+    """<J v, w> = <v, J^T w> for J = d(phi_T)/d(phi_0), and the eps^2
+    direction, with J v from forward-mode differentiation of the plain torch
+    forward (CPU, float64) and J^T w from the library's checkpointed adjoint."""
+    import torch
+    from torch_reference import forward as torch_forward
+    s, p = _problem(ace, orc, d, N, bc)
+    prm = s.params
+    eps2 = prm["eps"] ** 2
+    nsteps = 17
+    rng = np.random.default_rng(31 + d + bc)
+    phi0 = rng.uniform(-0.7, 0.7, p.shape)
+    v = rng.normal(size=p.shape)
+    w = rng.normal(size=p.shape)
+
+    def fwd(x, e2):
+        return torch_forward(x, e2, prm["dt"], prm["dx"], bc, nsteps)
+
+    x = torch.tensor(phi0)
+    e2 = torch.tensor(eps2, dtype=torch.float64)
+    _, jv = torch.func.jvp(fwd, (x, e2), (torch.tensor(v), torch.zeros((), dtype=torch.float64)))
+    _, je = torch.func.jvp(fwd, (x, e2), (torch.zeros_like(x), torch.ones((), dtype=torch.float64)))
+    g, ge = s.adjoint(phi0, nsteps, 5, w)
+    lhs = float(torch.sum(jv * torch.tensor(w)))
+    rhs = float(np.sum(v * g))
+    assert rhs == pytest.approx(lhs, rel=1e-12, abs=1e-12 * np.abs(v * g).sum())
+    lhs_e = float(torch.sum(je * torch.tensor(w)))
+    assert ge == pytest.approx(lhs_e, rel=1e-10)
+    s.close()

@@ -258,6 +258,34 @@ def _args_pop(s):
     return (d, N, [0.0] * d, [n * prm["dx"] for n in N], prm["eps"], prm["dt"], prm["bc"])
 
 
+@pytest.mark.parametrize("d,bc,N", [(2, 0, 70), (2, 1, 131), (2, 2, 45), (3, 0, 21), (3, 1, 33), (3, 2, 45)])
+def test_no_kernel_touches_memory_outside_the_fields(ace, orc, d, bc, N):
+    """Both field buffers are bound inside larger tensors whose margins hold
+    NaN; after every kernel choice (and depth) has stepped and monitored the
+    field, the margins are still NaN (no write outside a field) and the result
+    equals the oracle (no read of a margin)."""
+    import torch
+    s, p = _pair(ace, orc, d, N, bc)
+    n = s.total
+    guard = 4096
+    big = [torch.full((n + 2 * guard,), float("nan"), dtype=torch.float64, device="cuda") for _ in range(2)]
+    s.bind_fields(big[0][guard:guard + n], big[1][guard:guard + n])
+    phi0 = np.random.default_rng(N + bc).uniform(-1, 1, p.shape)
+    want, Ew, _ = p.run(phi0, 13, 4)
+    choices = [(ace.ACE_KERNEL_DIRECT, 0), (ace.ACE_KERNEL_TBLOCK, 0)]
+    choices += [(ace.ACE_KERNEL_MARCH, 0)] if d == 3 else [(ace.ACE_KERNEL_TBLOCK, k) for k in (1, 5, 12)]
+    for kernel, depth in choices:
+        s.set_kernel(kernel, depth)
+        s.set_phi0(phi0)
+        E, _ = s.run_monitored(13, 4)
+        np.testing.assert_allclose(s.get_phi(), want, rtol=0, atol=1e-13)
+        np.testing.assert_allclose(E, Ew, rtol=1e-12)
+        s.energy()
+        for t in big:
+            assert bool(torch.isnan(t[:guard]).all()) and bool(torch.isnan(t[guard + n:]).all()), (kernel, depth)
+    s.close()
+
+
 def test_condition_violation_negative_control(ace, orc):
     """kappa = 0.8209 at dt = 1/5 (Sec. 4.1.1): |xi| > 1 occurs, the guarded
     Newton loop still matches the oracle and the max-norm leaves [-1, 1]."""
