@@ -286,6 +286,47 @@ def test_no_kernel_touches_memory_outside_the_fields(ace, orc, d, bc, N):
     s.close()
 
 
+def test_failure_signals_and_resume(ace, orc):
+    """The monitored run's failure signals and checkpoint/resume.
+    - A field above 1 under the step condition: ACE_W_PHI0_GT1 when set,
+      ACE_W_MAXPRINCIPLE from the monitored run (Theorem 2's hypothesis fails).
+    - The fully explicit scheme far outside its condition overflows within a
+      few steps: ACE_E_NONFINITE.
+    - A run stopped after 20 steps and resumed from ace_get_phi in a new
+      handle ends bit for bit where the uninterrupted 37-step run ends."""
+    s, p = _pair(ace, orc, 2, 40, 0)
+    phi0 = np.random.default_rng(12).uniform(-1, 1, p.shape)
+    big = phi0.copy()
+    big[5, 7] = 1.5
+    assert s.set_phi0(big) == ace.ACE_W_PHI0_GT1
+    s.run_monitored(10, 5)
+    assert s.last_status == ace.ACE_W_MAXPRINCIPLE
+    f = ace.Solver(1, [64], [0.0], [1.0], 0.05, 0.9, 0)
+    f.set_scheme(ace.ACE_SCHEME_FEX)
+    f.set_phi0(np.random.default_rng(3).uniform(-1, 1, f.shape))
+    with pytest.raises(ace.AceError) as e:
+        f.run_monitored(60, 1)
+    assert e.value.code == ace.ACE_E_NONFINITE
+    f.close()
+    for d, N, bc in ((2, 40, 0), (3, 21, 2)):
+        a, q = _pair(ace, orc, d, N, bc)
+        x0 = np.random.default_rng(N).uniform(-1, 1, q.shape)
+        a.set_phi0(x0)
+        a.step(37)
+        whole = a.get_phi()
+        a.set_phi0(x0)
+        a.step(20)
+        ckpt = a.get_phi()
+        assert a.step_count == 20
+        b, _ = _pair(ace, orc, d, N, bc)
+        b.set_phi0(ckpt)
+        b.step(17)
+        assert np.array_equal(b.get_phi(), whole)
+        a.close()
+        b.close()
+    s.close()
+
+
 def test_condition_violation_negative_control(ace, orc):
     """kappa = 0.8209 at dt = 1/5 (Sec. 4.1.1): |xi| > 1 occurs, the guarded
     Newton loop still matches the oracle and the max-norm leaves [-1, 1]."""
