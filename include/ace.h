@@ -370,6 +370,11 @@ int ace_batch_autotune(ace_batch *b, int64_t trial_steps, char *json, size_t cap
  * (d, bc, shape) reuse it. */
 int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap);
 
+/* Diagnostics: if the environment variable ACE_LOG is set, the library
+ * prints one "[ace]" line on stderr per HIP error, handle creation (derived
+ * parameters, Newton count), graph capture (launch configuration) and
+ * autotuner choice. */
+
 /* Library version string. */
 const char *ace_version(void);
 

@@ -22,11 +22,17 @@ using namespace ace;
 
 namespace ace {
 
+bool log_enabled()
+{
+    static const bool on = getenv("ACE_LOG") != nullptr;
+    return on;
+}
+
 int hip_status(hipError_t e)
 {
     if (e == hipSuccess) return ACE_OK;
     if (e == hipErrorOutOfMemory) return ACE_E_NOMEM;
-    if (getenv("ACE_LOG")) fprintf(stderr, "[ace] HIP error: %s\n", hipGetErrorString(e));
+    if (log_enabled()) fprintf(stderr, "[ace] HIP error: %s\n", hipGetErrorString(e));
     return ACE_E_HIP;
 }
 
@@ -384,6 +390,9 @@ int graph_for(ace_solver *s, int kernel, hipGraphExec_t *out)
         return hip_status(ie);
     }
     s->graphs.push_back({kernel, s->zchunk, s->depth2, cur0, s->buf[0], s->buf[1], g, e});
+    if (log_enabled())
+        fprintf(stderr, "[ace] graph: %lld launches of kernel %d, %d step(s) each (plane chunk %d, 2D depth %d)\n",
+                (long long)s->graph_launches, kernel, per, s->zchunk, s->depth2);
     *out = e;
     return ACE_OK;
 }
@@ -534,6 +543,10 @@ int ace_create(int d, const int64_t *N, const double *L, const double *R, double
         ace_destroy(s);
         return hip_status(e);
     }
+    if (log_enabled())
+        fprintf(stderr, "[ace] create d=%d bc=%d M=%lldx%lldx%lld dx=%.6g kappa=%.6g h=%.6g Newton steps %d%s%s\n",
+                p.d, p.bc, (long long)p.M[0], (long long)p.M[1], (long long)p.M[2], p.dx, p.kappa, p.h, p.nit,
+                p.start2 ? " (second-order start)" : "", p.cond_ok ? "" : ", outside Theorem 2's conditions");
     *out = s;
     return rc;
 }
@@ -933,6 +946,12 @@ int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap)
              best.kernel, best.zchunk, best.depth2, best_ms);
     rec += buf;
     if (json && cap > 0) snprintf(json, cap, "%s", rec.c_str());
+    if (log_enabled())
+        fprintf(stderr,
+                "[ace] autotune d=%d bc=%d M=%lldx%lldx%lld: kernel %d, plane chunk %d, 2D depth %d, "
+                "%.6f ms/step\n",
+                s->p.d, s->p.bc, (long long)s->p.M[0], (long long)s->p.M[1], (long long)s->p.M[2], best.kernel,
+                best.zchunk, best.depth2, best_ms);
     const char *path = getenv("ACE_AUTOTUNE_CACHE");
     if (path) {
         FILE *f = fopen(path, "a");

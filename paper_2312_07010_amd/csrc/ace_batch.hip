@@ -683,6 +683,9 @@ int ace_batch_autotune(ace_batch *b, int64_t trial_steps, char *json, size_t cap
     if (rc < 0) return rc;
     rec += "], \"choice\": {\"resident_limit\": " + std::to_string(best_lim) +
            ", \"depth\": " + std::to_string(best_depth) + "}}";
+    if (log_enabled())
+        fprintf(stderr, "[ace] batch autotune (%d instances): LDS limit %lld nodes, region depth %d, %.4f ms\n",
+                b->count, (long long)best_lim, best_depth, best_ms);
     if (json && cap > 0) snprintf(json, cap, "%s", rec.c_str());
     return ACE_OK;
 }

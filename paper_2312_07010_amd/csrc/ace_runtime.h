@@ -19,6 +19,10 @@ struct Problem {
     int scheme;  // ACE_SCHEME_*
 };
 
+// True if the environment variable ACE_LOG is set: the library then reports
+// HIP errors, handle parameters, graph captures and autotuner choices on
+// stderr, one "[ace]" line each.
+bool log_enabled();
 int hip_status(hipError_t e);
 int64_t nodes_per_axis(int64_t N, int bc);
 // Newton steps that bring the root iteration (first- or second-order start)

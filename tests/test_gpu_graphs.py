@@ -64,3 +64,32 @@ def test_graph_dropped_when_eps_changes(ace):
         s.set_eps(0.013)
         s.step(20)
     assert np.array_equal(a.get_phi(), b.get_phi())
+
+
+def test_log_lines(ace):
+    """With ACE_LOG set, handle creation, a graph capture and the autotuner's
+    choice each print one "[ace]" line on stderr (a child process, since the
+    library reads the variable once per process)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import numpy as np\n"
+        "from paper_2312_07010_amd import ace\n"
+        "s = ace.Solver(2, [62, 62], [0.0, 0.0], [1.0, 1.0], 0.02, 1e-3, 'HN')\n"
+        "s.set_phi0(np.zeros(s.shape))\n"
+        "s.autotune(5)\n"
+        "s.set_kernel(ace.ACE_KERNEL_DIRECT)\n"
+        "s.step(200)\n"
+        "s.get_phi()\n"
+        "s.close()\n" % root)
+    env = dict(os.environ, ACE_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [ln for ln in r.stderr.splitlines() if ln.startswith("[ace]")]
+    assert any(ln.startswith("[ace] create d=2 bc=0 M=64x64x1") for ln in lines), lines
+    assert any(ln.startswith("[ace] autotune d=2") for ln in lines), lines
+    assert any(ln.startswith("[ace] graph: ") for ln in lines), lines
+    assert not any("HIP error" in ln for ln in lines), lines
