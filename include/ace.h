@@ -366,7 +366,8 @@ int ace_batch_autotune(ace_batch *b, int64_t trial_steps, char *json, size_t cap
  * Keeps the fastest as the ACE_KERNEL_AUTO choice, restores the field, and
  * writes a one-line JSON record of the timings into json (capacity cap
  * bytes, may be NULL).  If the environment variable ACE_AUTOTUNE_CACHE names
- * a file, the choice is appended there and later handles of the same
+ * a file, the choice is appended there (one JSON object per line: d, bc, M,
+ * kernel, zchunk, depth2, ms_per_step) and later handles of the same
  * (d, bc, shape) reuse it. */
 int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap);
 

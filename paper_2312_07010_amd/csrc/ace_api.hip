@@ -464,23 +464,27 @@ int monitor_now(ace_solver *s, double *dev_out)
     return ACE_OK;
 }
 
-// Autotuner cache: one line per tuned problem shape,
-//   ace-tune <d> <bc> <M0> <M1> <M2> <kernel> <zchunk> <depth2> <ms_per_step>
-// appended by ace_autotune; the last matching line wins.
+// Autotuner cache: one JSON object per line and tuned problem shape,
+//   {"d": 2, "bc": 0, "M": [1024, 1024, 1], "kernel": 4, "zchunk": 32,
+//    "depth2": 5, "ms_per_step": 0.003389}
+// appended by ace_autotune (kTuneFormat) and read back with the same format;
+// the last matching line wins, other lines are skipped.
+constexpr const char *kTuneFormat =
+    "{\"d\": %d, \"bc\": %d, \"M\": [%lld, %lld, %lld], \"kernel\": %d, \"zchunk\": %d, "
+    "\"depth2\": %d, \"ms_per_step\": %lf}";
+
 void load_tuning(ace_solver *s)
 {
     const char *path = getenv("ACE_AUTOTUNE_CACHE");
     if (!path) return;
     FILE *f = fopen(path, "r");
     if (!f) return;
-    char line[256];
+    char line[512];
     while (fgets(line, sizeof line, f)) {
         int d, bc, k, zc, k2;
         long long m0, m1, m2;
         double ms;
-        if (sscanf(line, "ace-tune %d %d %lld %lld %lld %d %d %d %lf", &d, &bc, &m0, &m1, &m2, &k,
-                   &zc, &k2, &ms) != 9)
-            continue;
+        if (sscanf(line, kTuneFormat, &d, &bc, &m0, &m1, &m2, &k, &zc, &k2, &ms) != 9) continue;
         if (d == s->p.d && bc == s->p.bc && m0 == s->p.M[0] && m1 == s->p.M[1] && m2 == s->p.M[2] &&
             k >= ACE_KERNEL_DIRECT && k <= ACE_KERNEL_TBLOCK &&
             (zc == 0 || zc >= TBLOCK_MIN_ZCHUNK) && k2 >= 1 && k2 <= tblock2d_max_depth()) {
@@ -956,9 +960,12 @@ int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap)
     if (path) {
         FILE *f = fopen(path, "a");
         if (f) {
-            fprintf(f, "ace-tune %d %d %lld %lld %lld %d %d %d %.6f\n", s->p.d, s->p.bc,
-                    (long long)s->p.M[0], (long long)s->p.M[1], (long long)s->p.M[2], best.kernel,
-                    best.zchunk, best.depth2, best_ms);
+            // the same fields as kTuneFormat, ms written with a fixed precision
+            fprintf(f,
+                    "{\"d\": %d, \"bc\": %d, \"M\": [%lld, %lld, %lld], \"kernel\": %d, \"zchunk\": %d, "
+                    "\"depth2\": %d, \"ms_per_step\": %.6f}\n",
+                    s->p.d, s->p.bc, (long long)s->p.M[0], (long long)s->p.M[1], (long long)s->p.M[2],
+                    best.kernel, best.zchunk, best.depth2, best_ms);
             fclose(f);
         }
     }

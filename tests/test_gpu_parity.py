@@ -163,6 +163,8 @@ def test_autotune_restores_the_field_and_keeps_results(ace, orc, d, N, bc, tmp_p
     t = ace.Solver(*args)
     assert t.get_kernel() == s.get_kernel()
     t.close()
+    cached = [json.loads(ln) for ln in (tmp_path / "tune.txt").read_text().splitlines()]
+    assert cached[-1]["M"][:d] == list(p.shape) and cached[-1]["kernel"] == ch["kernel"]
     s.close()
 
 
