@@ -203,6 +203,7 @@ def test_adjoint_state_errors(ace, orc):
     s.close()
 
 
+@pytest.mark.filterwarnings("ignore::DeprecationWarning")  # raised inside torch.func
 @pytest.mark.parametrize("d,bc,N", [(1, 2, 40), (2, 0, 24), (2, 1, 23), (3, 2, 10)])
 def test_dot_product_against_torch_tangent(ace, orc, d, bc, N):
     """<J v, w> = <v, J^T w> for J = d(phi_T)/d(phi_0), and the eps^2
