@@ -322,6 +322,9 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="REPS",
                     help="only copy a 1 GiB device buffer REPS times (a plain copy kernel of "
                          "known size, for scaling HBM counters) and report its bandwidth")
+    ap.add_argument("--only", choices=["adjoint", "batched"], default=None,
+                    help="run only the adjoint-ratio or the batched measurement (for profiling) "
+                         "and print its result")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -348,6 +351,15 @@ def main():
         ms = e0.elapsed_time(e1) / args.calibrate_copy
         print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n,
                           "avg_ms": ms, "GBps_read_plus_write": 16 * n / ms / 1e6}))
+        return
+
+    if args.only == "adjoint":
+        ratio, fwd_ms, bwd_ms, adj_kernel = adjoint_ratio(ace, torch)
+        print(json.dumps({"only": "adjoint", "adjoint_cost_ratio": ratio, "forward_ms": fwd_ms,
+                          "backward_ms": bwd_ms, "kernel": adj_kernel}), flush=True)
+        return
+    if args.only == "batched":
+        print(json.dumps(dict(only="batched", **batched_speedup(ace, torch))), flush=True)
         return
 
     if args.workload == "pop3d":
