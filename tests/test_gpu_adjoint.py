@@ -200,6 +200,12 @@ def test_adjoint_state_errors(ace, orc):
     g_or, _, ge_or = p.adjoint(phi0, 10, lam)
     np.testing.assert_allclose(g, g_or, rtol=0, atol=1e-13 * np.abs(g_or).max())
     assert ge == pytest.approx(ge_or, rel=1e-11)
+    # zero steps: phi_T = phi_0, so dL/dphi_0 = lambda_T and dL/deps^2 = 0
+    s.forward_ckpt(phi0, 0, 4)
+    np.testing.assert_array_equal(s.get_phi(), phi0)
+    g, ge = s.backward(lam)
+    np.testing.assert_array_equal(g, lam)
+    assert ge == 0.0
     s.close()
 
 

@@ -129,6 +129,9 @@ def test_batch_repeated_steps_and_rejects_bad_instances(ace):
     b.step(20)
     for x, y in zip(b.get_all(), two):
         assert np.array_equal(x, y)
+    b.step(0)  # zero steps leave every instance as it is
+    for x, y in zip(b.get_all(), two):
+        assert np.array_equal(x, y)
     bad = list(insts) + [(3, [8] * 3, [0] * 3, [1] * 3, 0.1, 1e-3, 0)]
     with pytest.raises(ace.AceError):
         ace.Batch(bad)
