@@ -79,14 +79,14 @@ def test_2d_neumann_1024_full(ace, orc, inputs):
     assert np.all(np.diff(E) <= 1e-14 * np.abs(E[:-1]))
 
 
-def _subbox_oracle(orc, w, phi0, centre, T, kappa, h):
+def _subbox_oracle(orc, w, phi0, centre, T, kappa, h, scheme=0):
     """Value of node `centre` after T steps of the periodic problem, computed
     by the oracle on the (2T+3)^3 box around it: nodes farther than T from
     the box surface cannot be reached by boundary effects in T steps."""
     B = 2 * T + 3
     idx = [np.arange(c - T - 1, c + T + 2) % n for c, n in zip(centre, phi0.shape)]
     box = phi0[np.ix_(*idx)]
-    q = orc.Problem(3, [B - 2] * 3, [0.0] * 3, [1.0] * 3, 0.1, 2 * h, "HN")
+    q = orc.Problem(3, [B - 2] * 3, [0.0] * 3, [1.0] * 3, 0.1, 2 * h, "HN", scheme=scheme)
     assert q.shape == box.shape
     q.kappa = kappa  # same lattice parameter as the full problem
     out, _, _ = q.run(box, T)
@@ -113,6 +113,28 @@ def test_3d_periodic_512_sampled(ace, orc, inputs):
         for c in samples:
             want = _subbox_oracle(orc, w, phi0, c, T, p.kappa, p.h)
             assert abs(got[c] - want) <= (2e-15 if T == 1 else 5e-14), (T, c, got[c], want)
+
+
+@pytest.mark.timeout(600)
+def test_3d_periodic_512_fex_sampled(ace, orc, inputs):
+    """The fully explicit comparison scheme on the benchmark field and kernel
+    (its extra line in the benchmark): sampled nodes after 1 and 20 steps."""
+    w = inputs.W3D
+    s = ace.Solver(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
+    p = orc.Problem(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
+    s.set_scheme(ace.ACE_SCHEME_FEX)
+    phi0 = w_field(w, s)
+    rng = np.random.default_rng(6)
+    samples = [tuple(int(v) for v in rng.integers(0, 512, 3)) for _ in range(16)]
+    samples += [(0, 0, 0), (511, 511, 511), (256, 256, 256 + 154), (256 - 154, 256, 256)]
+    s.set_phi0(phi0)
+    for T in (1, 20):
+        s.step(T - (1 if T == 20 else 0))
+        got = s.get_phi()
+        for c in samples:
+            want = _subbox_oracle(orc, w, phi0, c, T, p.kappa, p.h, scheme=1)
+            assert abs(got[c] - want) <= (2e-15 if T == 1 else 5e-14), (T, c, got[c], want)
+    s.close()
 
 
 @pytest.mark.timeout(600)
