@@ -138,6 +138,26 @@ def test_3d_periodic_512_fex_sampled(ace, orc, inputs):
 
 
 @pytest.mark.timeout(600)
+def test_3d_periodic_512_monitors(ace, orc, inputs):
+    """Energy, max-norm and phase volume of the benchmark field at full size:
+    the fused monitor of phi^0 in the two-step launch, the standalone pass on
+    phi^2, and the phase-volume pass, against the oracle's compensated sums."""
+    w = inputs.W3D
+    s = ace.Solver(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
+    p = orc.Problem(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
+    phi0 = w_field(w, s)
+    s.set_phi0(phi0)
+    assert s.phase_volume() == pytest.approx(p.phase_volume(phi0), rel=1e-13)
+    E, m = s.run_monitored(2, 2)
+    phi2, _, _ = p.run(phi0, 2)
+    assert E[0] == pytest.approx(p.energy(phi0), rel=1e-13)
+    assert m[0] == p.maxnorm(phi0)
+    assert E[1] == pytest.approx(p.energy(phi2), rel=1e-13)
+    assert m[1] == pytest.approx(p.maxnorm(phi2), abs=1e-15)
+    s.close()
+
+
+@pytest.mark.timeout(600)
 def test_3d_periodic_512_invariants_full_length(ace, inputs):
     """5000 steps at 512^3: the maximum principle and the energy law hold at
     every monitored step (Theorem 2's condition is satisfied)."""
