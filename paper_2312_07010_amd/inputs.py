@@ -3,7 +3,9 @@
 This module holds no arithmetic of the scheme.  It only draws initial fields
 and instance descriptors from seeded generators, so that the GPU library and
 the CPU oracle receive byte-identical inputs.  Node coordinates are passed in
-by the caller (each side computes its own layout).
+by the caller (each side computes its own layout).  The batched workload's
+time steps are defined as half the largest step the stability condition
+allows; that formula fixes an input here and takes no part in any step.
 
 Workloads mirror the paper's experiments (Sec. 4): uniform random fields as
 in the 1D Dirichlet example, smooth tanh interfaces as in the mean-curvature
