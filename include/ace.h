@@ -113,7 +113,9 @@ int ace_node_coords(const ace_solver *s, int axis, double *x);
 int ace_params(const ace_solver *s, ace_params_t *p);
 
 /* Runs all later device work of the handle on this HIP stream (hipStream_t,
- * may be NULL for the default stream). */
+ * may be NULL for the default stream).  Switching to another stream first
+ * waits for the old one and drops the graphs captured for it, so no replay
+ * still in flight there loses its graph. */
 int ace_set_stream(ace_solver *s, void *hip_stream);
 
 /* Uses caller-owned device buffers a, b (each ace_shape total doubles) as
@@ -185,9 +187,29 @@ int ace_step(ace_solver *s, int64_t nsteps);
  * maxn of length nsteps/every + 1 (every >= 1).  The monitors of the field
  * a step reads are fused into that step.  Synchronous.  Errors:
  * ACE_E_NONFINITE.  Warnings (conditions_ok only): ACE_W_MAXPRINCIPLE,
- * ACE_W_ENERGY_UP. */
+ * ACE_W_ENERGY_UP; when both occur the return value is ACE_W_MAXPRINCIPLE
+ * and ace_get_warnings reports both. */
 int ace_run_monitored(ace_solver *s, int64_t nsteps, int64_t every,
                       double *E, double *maxn);
+
+/* Bit of warning w in a warning mask. */
+#define ACE_WARN_BIT(w) (1 << (w))
+
+/* Every warning the last ace_run_monitored of the handle saw, as a mask of
+ * ACE_WARN_BIT(ACE_W_MAXPRINCIPLE) and ACE_WARN_BIT(ACE_W_ENERGY_UP) (0 if
+ * none or if no monitored run happened yet).  Host memory. */
+int ace_get_warnings(const ace_solver *s, int *mask);
+
+/* The check ace_run_monitored applies to its monitor series, on host
+ * arrays E and maxn of n >= 1 values (steps 0, every, 2 every, ...):
+ * under the step conditions (conditions_ok != 0) a max-norm above
+ * 1 + 4 u (u = 2^-53) violates Theorem 2 (Sec. 3.2) and an energy rise
+ * E[j] > E[j-1] + 1e-14 |E[j-1]| violates Theorem 3 (Sec. 3.3).  Writes
+ * the mask of every warning seen to *mask (may be NULL) and returns
+ * ACE_E_NONFINITE if any value is NaN or infinite, else ACE_W_MAXPRINCIPLE,
+ * else ACE_W_ENERGY_UP, else ACE_OK.  Host-only: no device is touched. */
+int ace_monitor_status(int64_t n, const double *E, const double *maxn,
+                       int conditions_ok, int *mask);
 
 /* Discrete energy of the current field (Sec. 3.3, Theorem 3):
  *   E = dx^d [ sum_i (phi_i^2 - 1)^2 / 4 - kappa/(2 dt) Phi^T Lambda Phi ],
@@ -206,6 +228,13 @@ int ace_maxnorm(ace_solver *s, double *m);
  * the mean-curvature examples (Sec. 4.2.2).  Deterministic reduction.
  * Synchronous; *V is host memory. */
 int ace_phase_volume(ace_solver *s, double *V);
+
+/* Radius of the shrinking circle / sphere of the mean-curvature examples
+ * (Sec. 4.2.2) from the phase volume V of ace_phase_volume: the radius of
+ * the disc (d = 2, V = pi R^2) or ball (d = 3, V = 4/3 pi R^3) holding it,
+ * and half the phase length (d = 1, V = 2 R).  Synchronous; *R is host
+ * memory.  Errors as ace_phase_volume. */
+int ace_equivalent_radius(ace_solver *s, double *R);
 
 /* Copies the current field (total doubles, C order) to out. */
 int ace_get_phi(ace_solver *s, double *out, int where);
@@ -249,6 +278,14 @@ int ace_forward_ckpt(ace_solver *s, const double *phi0, int where, int64_t nstep
                      int64_t ckpt_every);  /* ACE_E_STATE under ACE_SCHEME_FEX */
 int ace_backward(ace_solver *s, const double *lambdaT, double *dphi0, double *deps2,
                  int where);
+
+/* Generation of the handle's checkpoints: 0 before the first
+ * ace_forward_ckpt, then incremented by every successful ace_forward_ckpt.
+ * A caller that keeps several forward passes on one handle (e.g. an
+ * autograd graph with two of them) compares it with the value read after
+ * its own forward to know whether ace_backward would use its checkpoints
+ * or a later pass's.  Returns -1 for a NULL handle. */
+int64_t ace_ckpt_generation(const ace_solver *s);
 
 /* ---- mesoscopic form: populations of the DdQ(2d+1) lattice -------------- */
 
@@ -326,6 +363,8 @@ int ace_batch_destroy(ace_batch *b);
  * arena (for device-side initialisation). */
 int ace_batch_shape(const ace_batch *b, int i, int64_t M[3], int64_t *total,
                     int64_t *offset);
+/* Stream of the batch's launches; switching waits for the old stream first
+ * (as ace_set_stream). */
 int ace_batch_set_stream(ace_batch *b, void *hip_stream);
 /* Sets phi^0 of instance i (host or device pointer). */
 int ace_batch_set_phi0(ace_batch *b, int i, const double *phi0, int where);

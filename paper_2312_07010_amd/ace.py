@@ -18,6 +18,13 @@ ACE_OK = 0
 ACE_E_ARG, ACE_E_SIZE, ACE_E_ANISO, ACE_E_DT = -1, -2, -3, -4
 ACE_E_HIP, ACE_E_NOMEM, ACE_E_NONFINITE, ACE_E_STATE = -5, -6, -7, -8
 ACE_W_CONDITIONS, ACE_W_PHI0_GT1, ACE_W_MAXPRINCIPLE, ACE_W_ENERGY_UP = 1, 2, 3, 4
+
+
+def warn_bit(w):
+    """Bit of warning w in a warning mask (ACE_WARN_BIT)."""
+    return 1 << int(w)
+
+
 ACE_BC_HN, ACE_BC_HD, ACE_BC_P = 0, 1, 2
 BC = {"HN": ACE_BC_HN, "HD": ACE_BC_HD, "P": ACE_BC_P}
 ACE_HOST, ACE_DEVICE = 0, 1
@@ -83,6 +90,10 @@ _SIGS = {
     "ace_maxnorm": (ctypes.c_int, [_vp, _P(_dbl)]),
     "ace_get_phi": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
     "ace_phase_volume": (ctypes.c_int, [_vp, _P(_dbl)]),
+    "ace_equivalent_radius": (ctypes.c_int, [_vp, _P(_dbl)]),
+    "ace_get_warnings": (ctypes.c_int, [_vp, _P(ctypes.c_int)]),
+    "ace_monitor_status": (ctypes.c_int, [_i64, _P(_dbl), _P(_dbl), ctypes.c_int, _P(ctypes.c_int)]),
+    "ace_ckpt_generation": (_i64, [_vp]),
     "ace_step_count": (_i64, [_vp]),
     "ace_field_ptr": (_vp, [_vp]),
     "ace_adjoint": (ctypes.c_int, [_vp, _vp, _i64, _i64, _vp, _vp, _P(_dbl), ctypes.c_int]),
@@ -302,9 +313,17 @@ class Solver:
         return v.value
 
     def equivalent_radius(self):
-        """Radius of the disc (d = 2) or ball (d = 3) holding the phase volume."""
-        V = self.phase_volume()
-        return (V / np.pi) ** 0.5 if self.d == 2 else (3 * V / (4 * np.pi)) ** (1.0 / 3.0)
+        """Radius of the disc (d = 2) or ball (d = 3) holding the phase volume
+        (half the phase length for d = 1)."""
+        v = _dbl()
+        _check(lib().ace_equivalent_radius(self._h, ctypes.byref(v)), "ace_equivalent_radius")
+        return v.value
+
+    def warnings(self):
+        """Mask of every warning the last run_monitored saw (warn_bit)."""
+        m = ctypes.c_int()
+        _check(lib().ace_get_warnings(self._h, ctypes.byref(m)), "ace_get_warnings")
+        return m.value
 
     def get_phi(self, out=None):
         if out is not None and _is_device(out):
@@ -330,6 +349,10 @@ class Solver:
             a, p = _host(phi0, self.total)
             rc = lib().ace_forward_ckpt(self._h, p, ACE_HOST, int(nsteps), int(ckpt_every))
         return _check(rc, "ace_forward_ckpt")
+
+    @property
+    def ckpt_generation(self):
+        return int(lib().ace_ckpt_generation(self._h))
 
     def backward(self, lambdaT, dphi0=None):
         g = _dbl()
@@ -360,6 +383,16 @@ class Solver:
         buf = ctypes.create_string_buffer(4096)
         _check(lib().ace_autotune(self._h, int(trial_steps), buf, 4096), "ace_autotune")
         return buf.value.decode()
+
+
+def monitor_status(E, maxn, conditions_ok=True):
+    """The library's check of a monitor series (host only): (status, mask)."""
+    E, _ = _host(E)
+    mx, _ = _host(maxn, E.size)
+    m = ctypes.c_int()
+    rc = lib().ace_monitor_status(E.size, E.ctypes.data_as(_P(_dbl)), mx.ctypes.data_as(_P(_dbl)),
+                                  int(bool(conditions_ok)), ctypes.byref(m))
+    return rc, m.value
 
 
 class Batch:

@@ -34,15 +34,27 @@ def link_command(objs, out=LIB):
     return [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", out] + objs
 
 
-def build(verbose: bool = False, jobs: int = 0) -> str:
+def _stale(src, obj, deps):
+    """True if obj is missing or older than src or any header in deps."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(p) > t for p in [src] + deps)
+
+
+def build(verbose: bool = False, jobs: int = 0, incremental: bool = False) -> str:
+    """Compiles every source (incremental: only sources newer than their
+    object or changed headers) and links libace.so."""
     os.makedirs(OBJ, exist_ok=True)
     srcs = sources()
     objs = [os.path.join(OBJ, os.path.basename(s)[:-4] + ".o") for s in srcs]
-    cmds = [compile_command(s, o) for s, o in zip(srcs, objs)]
+    headers = glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(INCLUDE, "*.h"))
+    pairs = [(s, o) for s, o in zip(srcs, objs) if not incremental or _stale(s, o, headers)]
+    cmds = [compile_command(s, o) for s, o in pairs]
     if verbose:
         for c in cmds:
             print(" ".join(c), flush=True)
-    jobs = jobs or min(len(cmds), os.cpu_count() or 1, 8)
+    jobs = jobs or max(1, min(len(cmds), os.cpu_count() or 1, 8))
     with ThreadPoolExecutor(max_workers=jobs) as pool:
         results = list(pool.map(lambda c: subprocess.run(c, capture_output=True, text=True), cmds))
     for c, r in zip(cmds, results):
@@ -60,4 +72,5 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    import sys
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

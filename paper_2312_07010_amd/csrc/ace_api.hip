@@ -189,10 +189,18 @@ StepCoef coef_of(const Problem &p)
     return c;
 }
 
+void energy_coefs(const Problem &p, double *dxd, double *cg)
+{
+    *dxd = pow(p.dx, p.d);
+    *cg = p.kappa / (2.0 * p.dt);
+}
+
 double energy_from(const Problem &p, const double *trip)
 {
     // E = dx^d [ sum (phi^2-1)^2/4 + kappa/(2 dt) sum_edges (dphi)^2 ]
-    return pow(p.dx, p.d) * (trip[0] + p.kappa / (2.0 * p.dt) * trip[1]);
+    double dxd, cg;
+    energy_coefs(p, &dxd, &cg);
+    return dxd * (trip[0] + cg * trip[1]);
 }
 
 int grow(double **ptr, int64_t *cap, int64_t need)
@@ -238,6 +246,7 @@ struct ace_solver {
     int64_t mon_cap = 0;
     double *pinned = nullptr;  // host pinned scratch (3 doubles)
     int64_t steps = 0;
+    int warn_mask = 0;  // warnings of the last monitored run (ACE_WARN_BIT)
     int kernel = ACE_KERNEL_AUTO;
     int depth = 0;
     int zchunk = 32;  // planes per workgroup of the 3D temporal-blocking kernel (0: persistent)
@@ -248,6 +257,7 @@ struct ace_solver {
     int64_t ckpt_cap = 0;
     int64_t ck_every = 0, ck_steps = 0, ck_count = 0;
     int64_t ck_field_version = -1;
+    int64_t ck_generation = 0;  // incremented by every ace_forward_ckpt
     double *seg = nullptr;  // two segment buffers, (every + 1) states each
     int64_t seg_cap = 0;
     hipStream_t aux = nullptr;  // recompute stream of the pipelined reverse sweep
@@ -626,6 +636,8 @@ int ace_params(const ace_solver *s, ace_params_t *q)
 int ace_set_stream(ace_solver *s, void *st)
 {
     if (!s) return ACE_E_ARG;
+    // a replay on the old stream may still use a captured graph
+    if ((hipStream_t)st != s->stream) drop_graphs(s);
     s->stream = (hipStream_t)st;
     return ACE_OK;
 }
@@ -783,18 +795,36 @@ int ace_run_monitored(ace_solver *s, int64_t nsteps, int64_t every, double *E, d
     ACE_HIP(hipMemcpyAsync(trip.data(), s->mon, trip.size() * sizeof(double), hipMemcpyDeviceToHost,
                            s->stream));
     ACE_HIP(hipStreamSynchronize(s->stream));
-    int warn = ACE_OK;
     for (int64_t j = 0; j < nmon; ++j) {
         E[j] = energy_from(s->p, &trip[3 * j]);
         maxn[j] = trip[3 * j + 2];
-        if (!isfinite(maxn[j]) || !isfinite(E[j])) return ACE_E_NONFINITE;
-        if (s->p.cond_ok) {
-            if (maxn[j] > 1.0 + 4.0 * 0x1p-53 && warn == ACE_OK) warn = ACE_W_MAXPRINCIPLE;
-            if (j > 0 && E[j] > E[j - 1] + 1e-14 * fabs(E[j - 1]) && warn == ACE_OK)
-                warn = ACE_W_ENERGY_UP;
-        }
     }
-    return warn;
+    return ace_monitor_status(nmon, E, maxn, s->p.cond_ok, &s->warn_mask);
+}
+
+int ace_get_warnings(const ace_solver *s, int *mask)
+{
+    if (!s || !mask) return ACE_E_ARG;
+    *mask = s->warn_mask;
+    return ACE_OK;
+}
+
+int ace_monitor_status(int64_t n, const double *E, const double *maxn, int conditions_ok, int *mask)
+{
+    if (mask) *mask = 0;
+    if (n < 1 || !E || !maxn) return ACE_E_ARG;
+    int bits = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (!isfinite(maxn[j]) || !isfinite(E[j])) return ACE_E_NONFINITE;
+        if (!conditions_ok) continue;
+        // Theorem 2: |phi| <= 1 is kept; Theorem 3: the energy does not rise
+        if (maxn[j] > 1.0 + 4.0 * 0x1p-53) bits |= ACE_WARN_BIT(ACE_W_MAXPRINCIPLE);
+        if (j > 0 && E[j] > E[j - 1] + 1e-14 * fabs(E[j - 1])) bits |= ACE_WARN_BIT(ACE_W_ENERGY_UP);
+    }
+    if (mask) *mask = bits;
+    if (bits & ACE_WARN_BIT(ACE_W_MAXPRINCIPLE)) return ACE_W_MAXPRINCIPLE;
+    if (bits & ACE_WARN_BIT(ACE_W_ENERGY_UP)) return ACE_W_ENERGY_UP;
+    return ACE_OK;
 }
 
 int ace_energy(ace_solver *s, double *E)
@@ -829,6 +859,19 @@ int ace_phase_volume(ace_solver *s, double *V)
     ACE_TRY(read_triple(s, s->mon, t));
     *V = pow(s->p.dx, s->p.d) * t[0];
     return isfinite(*V) ? ACE_OK : ACE_E_NONFINITE;
+}
+
+int ace_equivalent_radius(ace_solver *s, double *R)
+{
+    if (!s || !R) return ACE_E_ARG;
+    double V = 0.0;
+    ACE_TRY(ace_phase_volume(s, &V));
+    // Sec. 4.2.2: the circle (V = pi R^2) and the sphere (V = 4/3 pi R^3);
+    // in 1D the phase is an interval of length 2R
+    if (s->p.d == 1) *R = 0.5 * V;
+    else if (s->p.d == 2) *R = sqrt(V / M_PI);
+    else *R = cbrt(3.0 * V / (4.0 * M_PI));
+    return isfinite(*R) ? ACE_OK : ACE_E_NONFINITE;
 }
 
 int ace_get_phi(ace_solver *s, double *out, int where)
@@ -1004,8 +1047,11 @@ int ace_forward_ckpt(ace_solver *s, const double *phi0, int where, int64_t nstep
     s->ck_steps = nsteps;
     s->ck_count = nck;
     s->ck_field_version = s->field_version;
+    s->ck_generation++;
     return rc;
 }
+
+int64_t ace_ckpt_generation(const ace_solver *s) { return s ? s->ck_generation : -1; }
 
 int ace_backward(ace_solver *s, const double *lambdaT, double *dphi0, double *deps2, int where)
 {

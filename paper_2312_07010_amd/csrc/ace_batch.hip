@@ -498,6 +498,8 @@ int ace_batch_shape(const ace_batch *b, int i, int64_t M[3], int64_t *total, int
 int ace_batch_set_stream(ace_batch *b, void *st)
 {
     if (!b) return ACE_E_ARG;
+    // a replay on the old stream may still use a captured graph
+    if ((hipStream_t)st != b->stream) drop_graphs(b);
     b->stream = (hipStream_t)st;
     return ACE_OK;
 }

@@ -33,6 +33,8 @@ int derive(int d, const int64_t *N, const double *L, const double *R, double eps
            int bc, Problem &p);
 Shape shape_of(const Problem &p);
 StepCoef coef_of(const Problem &p);
+// E = dxd (bulk + cg grad) with dxd = dx^d and cg = kappa / (2 dt).
+void energy_coefs(const Problem &p, double *dxd, double *cg);
 double energy_from(const Problem &p, const double *trip);
 // (Re)allocates *ptr to hold at least need doubles of device memory.
 int grow(double **ptr, int64_t *cap, int64_t need);

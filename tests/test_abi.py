@@ -63,3 +63,29 @@ def _create(ace, d, N, L, R, eps, dt, bc):
 ])
 def test_create_rejects_invalid_problems(ace, args, code):
     assert _create(ace, *args) == code
+
+
+def test_monitor_status_reports_every_warning(ace):
+    """The check ace_run_monitored applies to its monitor series (Theorem 2:
+    the max-norm stays <= 1; Theorem 3: the energy does not rise), fed with
+    synthetic series: each warning alone, both together (both bits, the
+    max-principle code returned), none without the step conditions, and
+    non-finite values."""
+    u = 2.0 ** -53
+    W_MP, W_EU = ace.ACE_W_MAXPRINCIPLE, ace.ACE_W_ENERGY_UP
+    b_mp, b_eu = ace.warn_bit(W_MP), ace.warn_bit(W_EU)
+    E_down = [3.0, 2.0, 1.0]
+    E_up = [3.0, 2.0, 2.0 + 3e-14 * 2.0]
+    m_ok = [1.0, 1.0 + 4 * u, 0.5]
+    m_bad = [1.0, 1.0 + 8 * u, 0.5]
+    assert ace.monitor_status(E_down, m_ok) == (ace.ACE_OK, 0)
+    assert ace.monitor_status(E_down, m_bad) == (W_MP, b_mp)
+    assert ace.monitor_status(E_up, m_ok) == (W_EU, b_eu)
+    assert ace.monitor_status(E_up, m_bad) == (W_MP, b_mp | b_eu)
+    # a rise within the 1e-14 relative slack is rounding, not a violation
+    assert ace.monitor_status([1.0, 1.0 + 5e-15], [1.0, 1.0]) == (ace.ACE_OK, 0)
+    # outside the step conditions the theorems promise nothing
+    assert ace.monitor_status(E_up, m_bad, conditions_ok=False) == (ace.ACE_OK, 0)
+    assert ace.monitor_status([1.0, float("nan")], [1.0, 1.0])[0] == ace.ACE_E_NONFINITE
+    assert ace.monitor_status([1.0, 1.0], [1.0, float("inf")])[0] == ace.ACE_E_NONFINITE
+    assert ace.monitor_status([], [])[0] == ace.ACE_E_ARG

@@ -240,3 +240,47 @@ def test_dot_product_against_torch_tangent(ace, orc, d, bc, N):
     lhs_e = float(torch.sum(je * torch.tensor(w)))
     assert ge == pytest.approx(lhs_e, rel=1e-10)
     s.close()
+
+
+def test_autograd_two_passes_on_one_solver(ace, orc):
+    """Two ace_evolve nodes on one solver handle (different phi0 and eps^2)
+    in one loss: the second forward replaces the first one's checkpoints, so
+    the first node's backward repeats its forward.  Both gradients match a
+    plain differentiable torch forward on the CPU and the oracle's adjoint."""
+    import torch
+    from paper_2312_07010_amd.autograd import ace_evolve
+    from torch_reference import forward as torch_forward
+    s, p = _problem(ace, orc, 2, 24, 0)
+    rng = np.random.default_rng(8)
+    pa, pb = rng.uniform(-0.5, 0.5, p.shape), rng.uniform(-0.5, 0.5, p.shape)
+    ta, tb = rng.uniform(-0.5, 0.5, p.shape), rng.uniform(-0.5, 0.5, p.shape)
+    e2a, e2b = p.eps ** 2, 1.2 * p.eps ** 2
+    n = 30
+    xa = torch.tensor(pa, device="cuda", requires_grad=True)
+    xb = torch.tensor(pb, device="cuda", requires_grad=True)
+    ea = torch.tensor(e2a, dtype=torch.float64, device="cuda", requires_grad=True)
+    eb = torch.tensor(e2b, dtype=torch.float64, device="cuda", requires_grad=True)
+    oa = ace_evolve(xa, ea, s, n, 8)
+    ob = ace_evolve(xb, eb, s, n, 8)
+    loss = 0.5 * torch.sum((oa - torch.tensor(ta, device="cuda")) ** 2) + \
+        0.5 * torch.sum((ob - torch.tensor(tb, device="cuda")) ** 2)
+    loss.backward()
+    # reference: autograd through an independent torch forward (CPU, float64)
+    ra = torch.tensor(pa, requires_grad=True)
+    rb = torch.tensor(pb, requires_grad=True)
+    rea = torch.tensor(e2a, dtype=torch.float64, requires_grad=True)
+    reb = torch.tensor(e2b, dtype=torch.float64, requires_grad=True)
+    ref = 0.5 * torch.sum((torch_forward(ra, rea, p.dt, p.dx, 0, n) - torch.tensor(ta)) ** 2) + \
+        0.5 * torch.sum((torch_forward(rb, reb, p.dt, p.dx, 0, n) - torch.tensor(tb)) ** 2)
+    ref.backward()
+    for got, want in ((xa.grad, ra.grad), (xb.grad, rb.grad)):
+        w = want.numpy()
+        np.testing.assert_allclose(got.cpu().numpy(), w, rtol=0, atol=1e-10 * np.abs(w).max())
+    assert ea.grad.item() == pytest.approx(rea.grad.item(), rel=1e-8)
+    assert eb.grad.item() == pytest.approx(reb.grad.item(), rel=1e-8)
+    # and the oracle's adjoint of the first pass
+    phiT, _, _ = p.run(pa, n)
+    g_or, _, ge_or = p.adjoint(pa, n, phiT - ta)
+    np.testing.assert_allclose(xa.grad.cpu().numpy(), g_or, rtol=0, atol=1e-12 * np.abs(g_or).max())
+    assert ea.grad.item() == pytest.approx(ge_or, rel=1e-10)
+    s.close()

@@ -93,3 +93,45 @@ def test_log_lines(ace):
     assert any(ln.startswith("[ace] autotune d=2") for ln in lines), lines
     assert any(ln.startswith("[ace] graph: ") for ln in lines), lines
     assert not any("HIP error" in ln for ln in lines), lines
+
+
+def test_stream_switch_keeps_replays_valid(ace):
+    """Switching the handle (and a batch) between two torch streams while
+    graph replays are queued: every result equals a run on one stream (the
+    switch waits for the old stream before its graphs are dropped)."""
+    import torch
+    args = (2, [200, 200], [0, 0], [1, 1], 0.01, 1e-3, 0)
+    ref = ace.Solver(*args)
+    ref.set_graph_launches(4)
+    sw = ace.Solver(*args)
+    sw.set_graph_launches(4)
+    phi0 = np.random.default_rng(5).uniform(-0.9, 0.9, ref.shape)
+    ref.set_phi0(phi0)
+    sw.set_phi0(phi0)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for rep in range(6):
+        with torch.cuda.stream(streams[rep % 2]):
+            sw.use_torch_stream()
+            sw.step(50)
+        ref.step(50)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(streams[0]):
+        sw.use_torch_stream()
+        got = sw.get_phi()
+    assert np.array_equal(got, ref.get_phi())
+    insts = [(1, [300], [0.0], [1.0], 0.02, 1e-3, "P"), (2, [120, 120], [0.0, 0.0], [1.0, 1.0], 0.01, 1e-3, "HN")]
+    b1 = ace.Batch(insts)
+    b2 = ace.Batch(insts)
+    fields = [np.random.default_rng(7 + i).uniform(-0.9, 0.9, shp) for i, shp in enumerate(b1.shapes)]
+    b1.set_all(fields)
+    b2.set_all(fields)
+    for rep in range(4):
+        with torch.cuda.stream(streams[rep % 2]):
+            b2.use_torch_stream()
+            b2.step(30)
+        b1.step(30)
+    torch.cuda.synchronize()
+    for i in range(len(insts)):
+        assert np.array_equal(b1.get_phi(i), b2.get_phi(i))
+    for x in (ref, sw, b1, b2):
+        x.close()

@@ -303,6 +303,10 @@ def test_failure_signals_and_resume(ace, orc):
     assert s.set_phi0(big) == ace.ACE_W_PHI0_GT1
     s.run_monitored(10, 5)
     assert s.last_status == ace.ACE_W_MAXPRINCIPLE
+    assert s.warnings() & ace.warn_bit(ace.ACE_W_MAXPRINCIPLE)
+    s.set_phi0(phi0)
+    s.run_monitored(10, 5)  # within [-1, 1] under the conditions: no warning left over
+    assert s.last_status == ace.ACE_OK and s.warnings() == 0
     f = ace.Solver(1, [64], [0.0], [1.0], 0.05, 0.9, 0)
     f.set_scheme(ace.ACE_SCHEME_FEX)
     f.set_phi0(np.random.default_rng(3).uniform(-1, 1, f.shape))
