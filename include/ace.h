@@ -229,6 +229,23 @@ int ace_maxnorm(ace_solver *s, double *m);
  * Synchronous; *V is host memory. */
 int ace_phase_volume(ace_solver *s, double *V);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * energy of ace_energy and the max-norm of ace_maxnorm, written to device
+ * memory out[0] (energy) and out[1] (max-norm) by kernels on the handle's
+ * stream, with no host synchronisation and no allocation.  phi is a device
+ * field of the handle's shape (total doubles, C order) or NULL for the
+ * handle's current field.  The per-block partial sums go to a static
+ * scratch array of 1.5 MiB that each device holds for the life of the
+ * process, shared by every handle on that device: calls that overlap on one
+ * device (on different streams, or from different threads) race, and must
+ * be ordered by the caller.  The values equal those of ace_energy and
+ * ace_maxnorm bit for bit.  Errors: ACE_E_ARG (NULL handle or out),
+ * ACE_E_SIZE (the field needs more than 65536 partial sums, about
+ * 2^31 nodes in 3D, 2^26 in 2D and 2^24 in 1D), ACE_E_STATE (the scratch
+ * address could not be looked up when the handle was created), ACE_E_HIP. */
+int ace_monitor_noalloc(ace_solver *s, const double *phi, double *out);
+
 /* Radius of the shrinking circle / sphere of the mean-curvature examples
  * (Sec. 4.2.2) from the phase volume V of ace_phase_volume: the radius of
  * the disc (d = 2, V = pi R^2) or ball (d = 3, V = 4/3 pi R^3) holding it,

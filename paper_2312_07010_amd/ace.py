@@ -93,6 +93,7 @@ _SIGS = {
     "ace_equivalent_radius": (ctypes.c_int, [_vp, _P(_dbl)]),
     "ace_get_warnings": (ctypes.c_int, [_vp, _P(ctypes.c_int)]),
     "ace_monitor_status": (ctypes.c_int, [_i64, _P(_dbl), _P(_dbl), ctypes.c_int, _P(ctypes.c_int)]),
+    "ace_monitor_noalloc": (ctypes.c_int, [_vp, _vp, _vp]),
     "ace_ckpt_generation": (_i64, [_vp]),
     "ace_step_count": (_i64, [_vp]),
     "ace_field_ptr": (_vp, [_vp]),
@@ -324,6 +325,15 @@ class Solver:
         m = ctypes.c_int()
         _check(lib().ace_get_warnings(self._h, ctypes.byref(m)), "ace_get_warnings")
         return m.value
+
+    def monitor_noalloc(self, out, phi=None):
+        """Energy and max-norm into the device tensor out[0:2] (float64),
+        stream-ordered, allocating nothing; phi: a device field of the
+        handle's shape, or None for the current field."""
+        po = _dev(out, 2)
+        pf = _dev(phi, self.total) if phi is not None else None
+        _check(lib().ace_monitor_noalloc(self._h, pf, po), "ace_monitor_noalloc")
+        return out
 
     def get_phi(self, out=None):
         if out is not None and _is_device(out):

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -219,6 +220,54 @@ int grow(double **ptr, int64_t *cap, int64_t need)
 }
 
 }  // namespace ace
+
+// ---------------------------------------------------------------------------
+// allocation-free monitor: device scratch held in a static array
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// Doubles of the static scratch: the reduced triple (kTripSlot doubles, so
+// the partials that follow stay 256-byte aligned) and up to kNoAllocParts
+// partial triples, 1.5 MiB per device for the life of the process.
+constexpr int64_t kTripSlot = 32;
+constexpr int64_t kNoAllocParts = 65536;
+constexpr int64_t kNoAllocDoubles = kTripSlot + 3 * kNoAllocParts;
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+// Device address of `scratch` on each device (host code must not pass the
+// array's name: on the host it is only a stand-in for the symbol).
+double *g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// Looks up the scratch address of the current device once; called by
+// ace_create with the handle's device current.
+void scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[dev]) return;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();  // leave no error behind for later launches
+        if (log_enabled())
+            fprintf(stderr, "[ace] scratch lookup on device %d failed: %s\n", dev, hipGetErrorString(e));
+        return;
+    }
+    g_scratch[dev] = (double *)ptr;
+}
+
+double *scratch_of(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch[dev];
+}
+
+}  // namespace
 
 #define ACE_TRY(expr)                  \
     do {                               \
@@ -546,6 +595,7 @@ int ace_create(int d, const int64_t *N, const double *L, const double *R, double
     s->shape = shape_of(p);
     s->coef = coef_of(p);
     (void)hipGetDevice(&s->device);
+    scratch_setup(s->device);
     const int arc = alloc_fields(s);
     if (arc < 0) {
         ace_destroy(s);
@@ -859,6 +909,23 @@ int ace_phase_volume(ace_solver *s, double *V)
     ACE_TRY(read_triple(s, s->mon, t));
     *V = pow(s->p.dx, s->p.d) * t[0];
     return isfinite(*V) ? ACE_OK : ACE_E_NONFINITE;
+}
+
+int ace_monitor_noalloc(ace_solver *s, const double *phi, double *out)
+{
+    if (!s || !out) return ACE_E_ARG;
+    double *scr = scratch_of(s->device);
+    if (!scr) return ACE_E_STATE;
+    const int64_t np = monitor_partials_needed(s->shape);
+    if (np < 1 || np > kNoAllocParts) return ACE_E_SIZE;
+    const double *f = phi ? phi : s->buf[s->cur];
+    int64_t n2 = 0;
+    ACE_HIP(launch_monitor(s->shape, f, scr + kTripSlot, &n2, s->stream));
+    ACE_HIP(launch_reduce(scr + kTripSlot, n2, scr, s->stream));
+    double dxd, cg;
+    energy_coefs(s->p, &dxd, &cg);
+    ACE_HIP(launch_monitor_finish(scr, dxd, cg, out, s->stream));
+    return ACE_OK;
 }
 
 int ace_equivalent_radius(ace_solver *s, double *R)

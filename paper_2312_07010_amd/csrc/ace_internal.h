@@ -48,6 +48,10 @@ hipError_t launch_monitor(const Shape &s, const double *in, double *partials,
                           int64_t *nparts, hipStream_t st);
 int64_t monitor_partials_needed(const Shape &s);
 
+// out[0] = dxd (trip[0] + cg trip[1]) (the energy), out[1] = trip[2].
+hipError_t launch_monitor_finish(const double *trip, double dxd, double cg, double *out,
+                                 hipStream_t st);
+
 // Fixed-order reduction of nparts triples to one triple at out[0..2].
 hipError_t launch_reduce(const double *partials, int64_t nparts, double *out,
                          hipStream_t st);

@@ -501,6 +501,24 @@ hipError_t launch_reduce(const double *partials, int64_t nparts, double *out, hi
     return hipGetLastError();
 }
 
+// E = dxd (bulk + cg grad) and the max-norm of a reduced monitor triple, on
+// the device (the same operations, in the same order, as the host's
+// energy_from, so both give the same bits).
+__global__ void k_monitor_finish(const double *__restrict__ trip, double dxd, double cg,
+                                 double *__restrict__ out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        out[0] = dxd * (trip[0] + cg * trip[1]);
+        out[1] = trip[2];
+    }
+}
+
+hipError_t launch_monitor_finish(const double *trip, double dxd, double cg, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_monitor_finish, dim3(1), dim3(64), 0, st, trip, dxd, cg, out);
+    return hipGetLastError();
+}
+
 int64_t phase_partials_needed() { return kPhaseBlocks; }
 
 hipError_t launch_phase_volume(const double *f, int64_t n, double *part, double *out, hipStream_t st)
