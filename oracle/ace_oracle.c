@@ -36,6 +36,11 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Loops over fewer nodes than this run on one thread: a parallel region per
+ * step of a small field costs more than it saves.  Results do not depend on
+ * the thread count. */
+#define ORACLE_PAR_MIN 16384
+
 #define BC_HN 0
 #define BC_HD 1
 #define BC_P 2
@@ -168,7 +173,7 @@ void oracle_xi(int d, const long *M, int bc, double kappa, double h,
     long st[3];
     strides(d, M, st);
     const long n = oracle_total(d, M);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= ORACLE_PAR_MIN)
     for (long i = 0; i < n; ++i)
         xi[i] = explicit_part(phi, d, M, st, bc, kappa, h, i);
 }
@@ -180,7 +185,7 @@ void oracle_step(int d, const long *M, int bc, double kappa, double h,
     long st[3];
     strides(d, M, st);
     const long n = oracle_total(d, M);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= ORACLE_PAR_MIN)
     for (long i = 0; i < n; ++i)
         out[i] = oracle_root(explicit_part(phi, d, M, st, bc, kappa, h, i), h);
 }
@@ -196,7 +201,7 @@ void oracle_step_fex(int d, const long *M, int bc, double kappa, double dt,
     long st[3];
     strides(d, M, st);
     const long n = oracle_total(d, M);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= ORACLE_PAR_MIN)
     for (long i = 0; i < n; ++i) {
         const double p = phi[i];
         double lap = 0.0;
@@ -400,7 +405,7 @@ int oracle_adjoint(int d, const long *M, int bc, double kappa, double dt,
 /* Roots for an array of explicit parts (used by the pins on the root).   */
 void oracle_root_array(long n, const double *xi, double h, double *out)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= ORACLE_PAR_MIN)
     for (long i = 0; i < n; ++i) out[i] = oracle_root(xi[i], h);
 }
 
@@ -432,7 +437,7 @@ void oracle_pop_moment(int d, const long *M, const double *f, double *phi)
 {
     const long n = oracle_total(d, M);
     const int q = 2 * d + 1;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= ORACLE_PAR_MIN)
     for (long i = 0; i < n; ++i) {
         double p = 0.0;
         for (int k = 0; k < q; ++k) p = p + f[k * n + i];
@@ -480,7 +485,7 @@ void oracle_pop_step(int d, const long *M, int bc, double omega1, double s,
     const double sA = (1.0 - s) / cs2;
     const double h = 0.5 * dt;
     const double w0 = 1.0 - 2.0 * d * omega1;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= ORACLE_PAR_MIN)
     for (long i = 0; i < n; ++i) {
         double rhs[7];
         const double p = phi[i];
