@@ -28,7 +28,7 @@ HBM_PEAK = 8.0e12            # MI355X HBM3E, bytes/s
 BYTES_PER_UPDATE = 16.0      # read phi^n + write phi^{n+1}
 CSRC = os.path.join(ROOT, "paper_2312_07010_amd", "csrc")
 KERNEL_SRC = {"k_march3d": "ace_march.hip", "k_tblock3d": "ace_tblock.hip",
-              "k_tblock2d": "ace_tblock2d.hip"}
+              "k_tblock2d": "ace_tblock2d.hip", "k_tb3": "ace_tb3.h"}
 
 
 def _sha(path):
@@ -36,10 +36,11 @@ def _sha(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def committed_counters(kname, plane_chunk):
+def committed_counters(kname, plane_chunk, region=None):
     """(figures for this launch shape, VALU peak) from the committed rocprofv3
     summary of the kernel, if it was taken on the current source of the kernel
-    and of the device header; else None."""
+    and of the device header; else None.  The 3D kernels are keyed by plane
+    chunk (and, for k_tb3, by depth, region rows and rows per thread)."""
     path = os.path.join(ROOT, "profiles", f"{kname}_p512_traffic.json")
     try:
         with open(path) as f:
@@ -49,16 +50,19 @@ def committed_counters(kname, plane_chunk):
         return None
     if t.get("kernel_src_sha") != src:
         return None
-    key = str(plane_chunk) if kname == "k_tblock3d" else "any"
+    if kname == "k_tb3":
+        key = "{}x{}x{}/{}".format(*region, plane_chunk)
+    else:
+        key = str(plane_chunk) if kname == "k_tblock3d" else "any"
     return t.get("by_plane_chunk", {}).get(key), t.get("valu_peak_lane_instr_per_s")
 
 
-def measured_traffic(kname, plane_chunk):
+def measured_traffic(kname, plane_chunk, region=None):
     """HBM bytes per launch of the step kernel from the committed rocprofv3
     FETCH_SIZE/WRITE_SIZE runs (scaled by a copy of known size), if they were
     taken on the current source of that kernel and of the device header and
-    at the same launch shape (planes per workgroup); else None."""
-    cc = committed_counters(kname, plane_chunk)
+    at the same launch shape (planes per workgroup, region); else None."""
+    cc = committed_counters(kname, plane_chunk, region)
     return cc[0].get("bytes_per_launch") if cc and cc[0] else None
 
 
@@ -242,8 +246,10 @@ WORKLOAD_DESC = {
 }
 
 
-def kernel_name(ace, d, kernel):
+def kernel_name(ace, d, kernel, region=None):
     if kernel == ace.ACE_KERNEL_TBLOCK:
+        if d == 3 and region is not None and region[1] > 0:
+            return "k_tb3"
         return "k_tblock3d" if d == 3 else "k_tblock2d"
     return {ace.ACE_KERNEL_MARCH: "k_march3d", ace.ACE_KERNEL_DIRECT: "k_step_direct",
             ace.ACE_KERNEL_RESIDENT: "k_resident"}.get(kernel, str(kernel))
@@ -261,7 +267,7 @@ def launches_in(steps, every, per_launch):
 
 
 def timed_workload(ace, torch, w, kernel="auto", plane_chunk=-1, autotune=True, steps=None,
-                   warmup=100, every=100, keep=False):
+                   warmup=100, every=100, keep=False, region3d=None):
     """ace_run_monitored(steps, every) on the workload's field, resident in
     HBM, after `warmup` untimed steps; timed by the host clock and by HIP
     events on the solver's stream (torch's current stream)."""
@@ -279,9 +285,13 @@ def timed_workload(ace, torch, w, kernel="auto", plane_chunk=-1, autotune=True, 
     tuning = None
     if plane_chunk >= 0:
         s.set_plane_chunk(plane_chunk)
+        if region3d:
+            s.set_kernel(ace.ACE_KERNEL_TBLOCK)
+            s.set_region3d(*region3d)
     elif kernel == "auto" and autotune:
         tuning = json.loads(s.autotune(20))
     k, per_launch = s.get_kernel()
+    region = s.get_region3d() if w.d == 3 else None
     s.set_phi0(phi0_dev)
     s.run_monitored(warmup, every)  # also loads every kernel variant used below
     torch.cuda.synchronize()
@@ -303,7 +313,7 @@ def timed_workload(ace, torch, w, kernel="auto", plane_chunk=-1, autotune=True, 
         launches = launches_in(steps, every, per_launch)
     r = {"solver": s if keep else None, "phi0": phi0, "phi0_dev": phi0_dev if keep else None,
          "n": float(s.total), "steps": steps, "wall": wall, "gpu_ms": gpu_ms,
-         "kernel": kernel_name(ace, w.d, k), "per_launch": per_launch,
+         "kernel": kernel_name(ace, w.d, k, region), "per_launch": per_launch, "region": region,
          "launches": launches, "plane_chunk": s.get_plane_chunk(),
          "tuning": tuning, "E": E, "mx": mx, "theorems_hold": ok}
     if not keep:
@@ -336,10 +346,16 @@ def timed_pop(ace, torch, w, steps=40, warmup=3):
     wall = time.perf_counter() - t0
     gpu_s = e0.elapsed_time(e1) / 1e3
     q, n = g.q, float(g.total)
+    # the carried form (the default for d >= 2) reads phi and writes the q
+    # populations and phi: 8 q + 16 bytes per node update; reading and
+    # writing all q populations (the fused form) would be 16 q
+    per = 8.0 * q + 16.0
     out = {"value": n * steps / wall, "unit": "grid-pt updates/s", "steps": steps,
            "ms_per_step": wall * 1e3 / steps, "avg_launch_us": gpu_s / steps * 1e6,
-           "populations": q, "bytes_per_update": 16.0 * q,
-           "roofline_frac": 16.0 * q * n * steps / gpu_s / HBM_PEAK,
+           "kernel": "k_pop_update, carried phi (1 step per launch)",
+           "populations": q, "bytes_per_update": per,
+           "roofline_frac": per * n * steps / gpu_s / HBM_PEAK,
+           "frac_at_16q_bytes": 16.0 * q * n * steps / gpu_s / HBM_PEAK,
            "device_bytes": g.device_bytes, "fd_device_bytes": int(2 * 8 * n)}
     g.close()
     return out
@@ -365,6 +381,9 @@ def main():
     ap.add_argument("--plane-chunk", type=int, default=-1, metavar="P",
                     help="fix the 3D blocked kernel's planes per workgroup, 0 = persistent grid "
                          "(skips the autotuner)")
+    ap.add_argument("--region3d", default="", metavar="D,R,T",
+                    help="with --plane-chunk: the 3D blocked kernel's depth D, region rows R and rows "
+                         "per thread T (2,0,0: the two-step kernel)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="REPS",
                     help="only copy a 1 GiB device buffer REPS times (a plain copy kernel of "
                          "known size, for scaling HBM counters) and report its bandwidth")
@@ -421,7 +440,7 @@ def main():
                        "nodes": int(np.prod(w.N)), "monitor_every": 0},
             "roofline": {"bound": "hbm", "achieved": r["roofline_frac"] * HBM_PEAK / 1e9,
                          "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": r["roofline_frac"],
-                         "traffic": None, "kernel": "k_pop_update, fused (1 step per launch)",
+                         "traffic": None, "kernel": r["kernel"],
                          "bytes_per_launch": r["bytes_per_update"] * np.prod(w.N),
                          "avg_launch_us": r["avg_launch_us"]},
             "population_rlb": r}), flush=True)
@@ -429,8 +448,9 @@ def main():
     w = {"3d": inputs.W3D, "2d": inputs.W2D, "1d": inputs.W1D}[args.workload]
     steps = args.steps or w.steps
     print(f"[bench] {w.name}: {steps} steps", file=sys.stderr, flush=True)
+    region3d = tuple(int(v) for v in args.region3d.split(",")) if args.region3d else None
     r = timed_workload(ace, torch, w, args.kernel, args.plane_chunk, not args.no_autotune, steps,
-                       args.warmup, args.every, keep=True)
+                       args.warmup, args.every, keep=True, region3d=region3d)
     s = r["solver"]
     n = r["n"]
     value = n * steps / r["wall"]
@@ -446,14 +466,23 @@ def main():
     avg_launch_s = r["gpu_ms"] / 1e3 / r["launches"]
     bytes_per_launch = BYTES_PER_UPDATE * n * r["per_launch"]
     achieved = bytes_per_launch / avg_launch_s
-    traffic = measured_traffic(r["kernel"], r["plane_chunk"])
+    traffic = measured_traffic(r["kernel"], r["plane_chunk"], r["region"])
     roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": achieved / HBM_PEAK, "traffic": traffic,
             "kernel": f"{r['kernel']} ({r['per_launch']} step(s) per launch)",
             "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_launch_s * 1e6}
+    if traffic:
+        # the counter-measured HBM bytes per launch over the same launch time:
+        # the bandwidth the kernel really draws (achieved/frac above count the
+        # algorithmic 16 B per node update, which temporal blocking undercuts)
+        roof["hbm_achieved_gbps"] = traffic / avg_launch_s / 1e9
+        roof["hbm_frac"] = traffic / avg_launch_s / HBM_PEAK
     if w.d == 3:
         roof["plane_chunk"] = r["plane_chunk"]
-    cc = committed_counters(r["kernel"], r["plane_chunk"])
+        if r["region"] and r["region"][1] > 0:
+            roof["region"] = {"depth": r["region"][0], "rows": r["region"][1], "cols": 64,
+                              "rows_per_thread": r["region"][2]}
+    cc = committed_counters(r["kernel"], r["plane_chunk"], r["region"])
     if cc and cc[0] and cc[1] and "sq_per_launch" in cc[0]:
         # VALU issue time of one launch (committed SQ_INSTS_VALU x 64 lanes at
         # the peak lane-instruction rate) over the launch time measured here

@@ -56,7 +56,7 @@ extern "C" {
 #define ACE_KERNEL_DIRECT 1  /* one thread per node, neighbours from cache    */
 #define ACE_KERNEL_MARCH 2   /* 3D: tiles marching along axis 0, LDS planes    */
 #define ACE_KERNEL_RESIDENT 3 /* whole field in LDS, many steps per launch    */
-#define ACE_KERNEL_TBLOCK 4  /* temporal blocking: 3D 2 steps per launch,
+#define ACE_KERNEL_TBLOCK 4  /* temporal blocking: 3D 2..4 steps per launch,
                                 2D 1..12 steps per launch                     */
 
 /* ---- schemes (ace_set_scheme) ------------------------------------------ */
@@ -145,11 +145,41 @@ int ace_set_graph_launches(ace_solver *s, int64_t launches);
 int ace_set_scheme(ace_solver *s, int scheme);
 
 /* Kernel choice for ace_step (ACE_KERNEL_*) and its temporal depth (steps
- * per launch; 0 = default).  ACE_KERNEL_TBLOCK accepts 0 or 2 in 3D and
- * 0..12 in 2D.  A choice that does not apply to the handle's dimension or
- * size falls back to ACE_KERNEL_DIRECT.  Every choice computes the same
- * result bit for bit.  Error: ACE_E_ARG for an unknown kernel or depth. */
+ * per launch; 0 = default).  ACE_KERNEL_TBLOCK accepts 0, 2, 3 or 4 in 3D
+ * (2: the two-step kernel; 3, 4: the configurable kernel on its default
+ * region for that depth, see ace_set_region3d) and 0..12 in 2D.  A choice
+ * that does not apply to the handle's dimension or size falls back to
+ * ACE_KERNEL_DIRECT.  Every choice computes the same result bit for bit.
+ * Error: ACE_E_ARG for an unknown kernel or depth. */
 int ace_set_kernel(ace_solver *s, int kernel, int depth);
+
+/* Temporal depth and region shape of the 3D blocked kernel (launch
+ * configuration only; results are unchanged bit for bit).  depth 2 with
+ * rows = rows_per_thread = 0 selects the two-step kernel (regions of
+ * 32 x 64 nodes, LDS planes double-buffered).  Otherwise (depth, rows,
+ * rows_per_thread) names one instantiated variant of the configurable
+ * kernel, which advances `depth` steps per launch on regions of rows x 64
+ * nodes held in registers, rows_per_thread consecutive rows per thread
+ * (rows / rows_per_thread wavefronts per workgroup), with a ring of depth
+ * nodes recomputed: (2, 32, 4), (3, 48, 3), (3, 48, 4), (3, 32, 2),
+ * (4, 32, 4), (4, 32, 2).  ace_autotune chooses among all of them.  Runs
+ * shorter than the depth take the two-step or one-step kernel.  Error:
+ * ACE_E_ARG when d != 3 or the triple is not instantiated. */
+int ace_set_region3d(ace_solver *s, int depth, int rows, int rows_per_thread);
+int ace_get_region3d(const ace_solver *s, int *depth, int *rows, int *rows_per_thread);
+
+/* Region shape of the 2D blocked kernel (launch configuration only; results
+ * are unchanged bit for bit).  rows = rows_per_thread = 0 selects the kernel
+ * that keeps each level's 32 x 64 region in LDS.  Otherwise (rows,
+ * rows_per_thread) names one instantiated variant of the register-resident
+ * kernel, which holds rows x 64 regions in registers, rows_per_thread
+ * consecutive rows per thread, neighbours along a row moved between lanes
+ * and across wavefronts through LDS edge rows: (32, 4), (32, 2), (64, 4),
+ * (16, 2).  Its depth (ace_set_kernel) is capped at rows / 2 - 4.
+ * ace_autotune chooses among all of them.  Error: ACE_E_ARG when d != 2 or
+ * the pair is not instantiated. */
+int ace_set_region2d(ace_solver *s, int rows, int rows_per_thread);
+int ace_get_region2d(const ace_solver *s, int *rows, int *rows_per_thread);
 
 /* Planes of axis 0 per workgroup of the 3D temporally blocked kernel
  * (launch shape only; results are unchanged).  0 selects a persistent grid:
@@ -334,12 +364,19 @@ int ace_pop_set_stream(ace_pop *p, void *hip_stream);
  * aligned tiles marching along axis 0 that sum phi of the tile and its ring
  * into LDS and write the new populations (16 (2d+1) bytes per node update);
  * ACE_POP_SPLIT a streaming pass writing phi = sum_k f_k, then the same
- * tiled update reading phi (16 (2d+1) + 16 bytes);
- * ACE_POP_AUTO: the fused form for d >= 2, direct for d = 1. */
+ * tiled update reading phi (16 (2d+1) + 16 bytes); ACE_POP_CARRY the same
+ * tiled update, which also writes phi of the new populations (the sum over
+ * k in the fixed order every moment here uses), so the next step reads phi
+ * alone: the regularized update depends on the populations only through
+ * phi (Sec. 2), and a step moves 8 (2d+1) + 16 bytes per node (one moment
+ * pass after ace_pop_set_phi0 / ace_pop_set_populations or another kernel's
+ * step; d >= 2, two more fields of device memory);
+ * ACE_POP_AUTO: the carried form for d >= 2, direct for d = 1. */
 #define ACE_POP_AUTO 0
 #define ACE_POP_DIRECT 1
 #define ACE_POP_FUSED 2
 #define ACE_POP_SPLIT 3
+#define ACE_POP_CARRY 4
 int ace_pop_set_kernel(ace_pop *p, int kernel);
 /* Populations at equilibrium f_k = w_k phi0 (phi0: total doubles, C order);
  * resets the step count.  ACE_E_NONFINITE for a non-finite host value. */
@@ -414,8 +451,10 @@ int ace_batch_autotune(ace_batch *b, int64_t trial_steps, char *json, size_t cap
 
 /* Times each kernel choice on the handle's problem for trial_steps steps
  * from the current field: the one-thread-per-node, LDS-resident (small
- * fields) and marching kernels, the 3D blocked kernel at several plane chunks
- * and as a persistent grid, and the 2D blocked kernel at depths 1-6, 8, 10, 12.  Each
+ * fields) and marching kernels, the 3D blocked kernels (the two-step kernel
+ * and every depth and region shape of ace_set_region3d) at several plane
+ * chunks and as a persistent grid, and the 2D blocked kernels (every region
+ * of ace_set_region2d) at depths 1-6, 8, 10, 12.  Each
  * trial is run once untimed and then timed; a trial shorter than 2 ms is
  * lengthened to about 2 ms (at most 2^20 steps), so that small fields are
  * timed in the steady state of a long run.  The trials time ace_step only.
@@ -423,7 +462,9 @@ int ace_batch_autotune(ace_batch *b, int64_t trial_steps, char *json, size_t cap
  * writes a one-line JSON record of the timings into json (capacity cap
  * bytes, may be NULL).  If the environment variable ACE_AUTOTUNE_CACHE names
  * a file, the choice is appended there (one JSON object per line: d, bc, M,
- * kernel, zchunk, depth2, ms_per_step) and later handles of the same
+ * kernel, zchunk, depth2, tb3 (the 3D variant, -1 for the two-step
+ * kernel), tb2 (the 2D variant, -1 for the LDS-plane kernel), ms_per_step)
+ * and later handles of the same
  * (d, bc, shape) reuse it. */
 int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap);
 

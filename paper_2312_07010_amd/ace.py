@@ -31,7 +31,7 @@ ACE_HOST, ACE_DEVICE = 0, 1
 ACE_KERNEL_AUTO, ACE_KERNEL_DIRECT, ACE_KERNEL_MARCH = 0, 1, 2
 ACE_KERNEL_RESIDENT, ACE_KERNEL_TBLOCK = 3, 4
 ACE_SCHEME_RLB_MIE, ACE_SCHEME_FEX = 0, 1
-ACE_POP_AUTO, ACE_POP_DIRECT, ACE_POP_FUSED, ACE_POP_SPLIT = 0, 1, 2, 3
+ACE_POP_AUTO, ACE_POP_DIRECT, ACE_POP_FUSED, ACE_POP_SPLIT, ACE_POP_CARRY = 0, 1, 2, 3, 4
 
 _i64 = ctypes.c_int64
 _dbl = ctypes.c_double
@@ -78,6 +78,10 @@ _SIGS = {
     "ace_bind_fields": (ctypes.c_int, [_vp, _vp, _vp]),
     "ace_set_kernel": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
     "ace_set_plane_chunk": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "ace_set_region3d": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "ace_get_region3d": (ctypes.c_int, [_vp, _P(ctypes.c_int), _P(ctypes.c_int), _P(ctypes.c_int)]),
+    "ace_set_region2d": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    "ace_get_region2d": (ctypes.c_int, [_vp, _P(ctypes.c_int), _P(ctypes.c_int)]),
     "ace_get_plane_chunk": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
     "ace_set_eps": (ctypes.c_int, [_vp, _dbl]),
     "ace_set_scheme": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -261,6 +265,25 @@ class Solver:
     def set_plane_chunk(self, planes):
         _check(lib().ace_set_plane_chunk(self._h, int(planes)), "ace_set_plane_chunk")
 
+    def set_region3d(self, depth, rows=0, rows_per_thread=0):
+        _check(lib().ace_set_region3d(self._h, int(depth), int(rows), int(rows_per_thread)),
+               "ace_set_region3d")
+
+    def get_region3d(self):
+        """(depth, rows, rows per thread) of the 3D blocked kernel."""
+        v = [ctypes.c_int() for _ in range(3)]
+        _check(lib().ace_get_region3d(self._h, *[ctypes.byref(x) for x in v]), "ace_get_region3d")
+        return tuple(x.value for x in v)
+
+    def set_region2d(self, rows=0, rows_per_thread=0):
+        _check(lib().ace_set_region2d(self._h, int(rows), int(rows_per_thread)), "ace_set_region2d")
+
+    def get_region2d(self):
+        """(rows, rows per thread) of the 2D blocked kernel ((0, 0): the LDS-plane kernel)."""
+        v = [ctypes.c_int() for _ in range(2)]
+        _check(lib().ace_get_region2d(self._h, *[ctypes.byref(x) for x in v]), "ace_get_region2d")
+        return tuple(x.value for x in v)
+
     def get_plane_chunk(self):
         p = ctypes.c_int()
         _check(lib().ace_get_plane_chunk(self._h, ctypes.byref(p)), "ace_get_plane_chunk")
@@ -390,8 +413,8 @@ class Solver:
         return out, g.value
 
     def autotune(self, trial_steps=20):
-        buf = ctypes.create_string_buffer(4096)
-        _check(lib().ace_autotune(self._h, int(trial_steps), buf, 4096), "ace_autotune")
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(lib().ace_autotune(self._h, int(trial_steps), buf, 1 << 16), "ace_autotune")
         return buf.value.decode()
 
 
@@ -502,8 +525,8 @@ class Batch:
         _check(lib().ace_batch_set_depth(self._h, int(depth)), "ace_batch_set_depth")
 
     def autotune(self, trial_steps=20):
-        buf = ctypes.create_string_buffer(4096)
-        _check(lib().ace_batch_autotune(self._h, int(trial_steps), buf, 4096), "ace_batch_autotune")
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(lib().ace_batch_autotune(self._h, int(trial_steps), buf, 1 << 16), "ace_batch_autotune")
         return buf.value.decode()
 
 

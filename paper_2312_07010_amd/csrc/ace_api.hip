@@ -300,6 +300,8 @@ struct ace_solver {
     int depth = 0;
     int zchunk = 32;  // planes per workgroup of the 3D temporal-blocking kernel (0: persistent)
     int depth2 = 5;   // steps per launch of the 2D temporal-blocking kernel (fastest on 1024^2)
+    int tb3 = -1;     // variant of the configurable 3D blocked kernel (-1: the two-step kernel)
+    int tb2 = -1;     // variant of the register-resident 2D blocked kernel (-1: the LDS-plane kernel)
     int tuned_kernel = 0;  // autotuned choice for ACE_KERNEL_AUTO (0: none)
     // reverse mode
     double *ckpt = nullptr;
@@ -321,7 +323,7 @@ struct ace_solver {
     int64_t graph_launches = 32;
     hipStream_t capture = nullptr;
     struct GraphEntry {
-        int kernel, zchunk, depth2, cur;
+        int kernel, zchunk, depth2, tb3, tb2, cur;
         const double *b0, *b1;
         hipGraph_t g;
         hipGraphExec_t e;
@@ -352,10 +354,34 @@ int effective_kernel(const ace_solver *s)
 }
 
 // Steps one launch of `kernel` advances (in a long enough run).
+// The register-resident 2D kernel is chosen and applies to the field.
+bool use_tb2(const ace_solver *s) { return s->p.d == 2 && s->tb2 >= 0 && tb2_supported(s->shape); }
+
 int steps_per_launch_of(const ace_solver *s, int kernel)
 {
     if (kernel != ACE_KERNEL_TBLOCK) return 1;
-    return (s->p.d == 3) ? 2 : s->depth2;
+    if (s->p.d == 3) return (s->tb3 >= 0 && tb3_supported(s->shape)) ? TB3_TABLE[s->tb3].depth : 2;
+    return use_tb2(s) ? std::min(s->depth2, tb2_max_depth(s->tb2)) : s->depth2;
+}
+
+// One launch of the handle's 2D blocked kernel (K steps; level_stride > 0:
+// every level written, as in launch_step_tblock2d).
+hipError_t launch_blocked2d(const ace_solver *s, const double *in, double *out, double *parts,
+                            int64_t *nparts, int K, int64_t level_stride, hipStream_t st)
+{
+    if (use_tb2(s)) return launch_step_tb2(s->tb2, s->shape, s->coef, in, out, parts, nparts, K, level_stride, st);
+    return launch_step_tblock2d(s->shape, s->coef, in, out, parts, nparts, K, level_stride, st);
+}
+
+int64_t blocked2d_blocks(const ace_solver *s, int K)
+{
+    return use_tb2(s) ? tb2_blocks(s->tb2, s->shape, K) : tblock2d_blocks(s->shape, K);
+}
+
+bool use_tb3(const ace_solver *s, int kernel, int64_t remaining)
+{
+    return kernel == ACE_KERNEL_TBLOCK && s->p.d == 3 && s->tb3 >= 0 && tb3_supported(s->shape) &&
+           remaining >= TB3_TABLE[s->tb3].depth;
 }
 
 // One launch from buf[cur] into buf[cur^1] advancing 1 step, or up to
@@ -367,7 +393,8 @@ int steps_per_launch_of(const ace_solver *s, int kernel)
 int64_t partials_for(const ace_solver *s, int kernel, int64_t remaining)
 {
     if (kernel == ACE_KERNEL_TBLOCK && s->p.d == 2)
-        return tblock2d_blocks(s->shape, (int)std::min<int64_t>(s->depth2, remaining));
+        return blocked2d_blocks(s, (int)std::min<int64_t>(steps_per_launch_of(s, kernel), remaining));
+    if (use_tb3(s, kernel, remaining)) return tb3_partials_needed(s->tb3, s->shape, s->zchunk);
     if (kernel == ACE_KERNEL_TBLOCK && remaining >= 2) return tblock_partials_needed(s->shape, s->zchunk);
     if (kernel == ACE_KERNEL_MARCH || kernel == ACE_KERNEL_TBLOCK) return march_partials_needed(s->shape);
     return direct_partials_needed(s->shape);
@@ -382,8 +409,11 @@ int launch_steps(ace_solver *s, int kernel, int64_t remaining, bool want_mon, in
     hipError_t e;
     int taken = 1;
     if (kernel == ACE_KERNEL_TBLOCK && s->p.d == 2) {
-        taken = (int)std::min<int64_t>(s->depth2, remaining);
-        e = launch_step_tblock2d(s->shape, s->coef, in, out, parts, nparts, taken, 0, s->stream);
+        taken = (int)std::min<int64_t>(steps_per_launch_of(s, kernel), remaining);
+        e = launch_blocked2d(s, in, out, parts, nparts, taken, 0, s->stream);
+    } else if (use_tb3(s, kernel, remaining)) {
+        e = launch_step_tb3(s->tb3, s->shape, s->coef, in, out, parts, nparts, s->zchunk, s->stream);
+        taken = TB3_TABLE[s->tb3].depth;
     } else if (kernel == ACE_KERNEL_TBLOCK && remaining >= 2) {
         e = launch_step_tblock2(s->shape, s->coef, in, out, parts, nparts, s->zchunk, s->stream);
         taken = 2;
@@ -415,7 +445,8 @@ void drop_graphs(ace_solver *s)
 int graph_for(ace_solver *s, int kernel, hipGraphExec_t *out)
 {
     for (auto &g : s->graphs)
-        if (g.kernel == kernel && g.zchunk == s->zchunk && g.depth2 == s->depth2 && g.cur == s->cur &&
+        if (g.kernel == kernel && g.zchunk == s->zchunk && g.depth2 == s->depth2 && g.tb3 == s->tb3 &&
+            g.tb2 == s->tb2 && g.cur == s->cur &&
             g.b0 == s->buf[0] && g.b1 == s->buf[1]) {
             *out = g.e;
             return ACE_OK;
@@ -448,10 +479,12 @@ int graph_for(ace_solver *s, int kernel, hipGraphExec_t *out)
         (void)hipGraphDestroy(g);
         return hip_status(ie);
     }
-    s->graphs.push_back({kernel, s->zchunk, s->depth2, cur0, s->buf[0], s->buf[1], g, e});
+    s->graphs.push_back({kernel, s->zchunk, s->depth2, s->tb3, s->tb2, cur0, s->buf[0], s->buf[1], g, e});
     if (log_enabled())
-        fprintf(stderr, "[ace] graph: %lld launches of kernel %d, %d step(s) each (plane chunk %d, 2D depth %d)\n",
-                (long long)s->graph_launches, kernel, per, s->zchunk, s->depth2);
+        fprintf(stderr,
+                "[ace] graph: %lld launches of kernel %d, %d step(s) each (plane chunk %d, 2D depth %d, "
+                "3D variant %d)\n",
+                (long long)s->graph_launches, kernel, per, s->zchunk, s->depth2, s->tb3);
     *out = e;
     return ACE_OK;
 }
@@ -498,8 +531,16 @@ int alloc_fields(ace_solver *s)
     if (march_supported(s->shape)) need2 = std::max<int64_t>(need2, 3 * march_partials_needed(s->shape));
     if (tblock_supported(s->shape))
         need2 = std::max<int64_t>(need2, 3 * tblock_partials_needed(s->shape, TBLOCK_MIN_ZCHUNK));
-    if (tblock2d_supported(s->shape))
+    if (tb3_supported(s->shape))
+        for (int v = 0; v < TB3_VARIANTS; ++v)
+            need2 = std::max<int64_t>(need2, 3 * std::max<int64_t>(tb3_partials_needed(v, s->shape, 0),
+                                                                 tb3_partials_needed(v, s->shape, TBLOCK_MIN_ZCHUNK)));
+    if (tblock2d_supported(s->shape)) {
         need2 = std::max<int64_t>(need2, 3 * tblock2d_blocks(s->shape, tblock2d_max_depth()));
+        if (tb2_supported(s->shape))
+            for (int v = 0; v < TB2_VARIANTS; ++v)
+                need2 = std::max<int64_t>(need2, 3 * tb2_blocks(v, s->shape, tb2_max_depth(v)));
+    }
     ACE_TRY(grow(&s->partials, &s->partials_cap, need2));
     ACE_HIP(hipHostMalloc((void **)&s->pinned, 64 * sizeof(double), hipHostMallocDefault));
     return ACE_OK;
@@ -525,12 +566,12 @@ int monitor_now(ace_solver *s, double *dev_out)
 
 // Autotuner cache: one JSON object per line and tuned problem shape,
 //   {"d": 2, "bc": 0, "M": [1024, 1024, 1], "kernel": 4, "zchunk": 32,
-//    "depth2": 5, "ms_per_step": 0.003389}
+//    "depth2": 5, "tb3": -1, "tb2": 0, "ms_per_step": 0.003389}
 // appended by ace_autotune (kTuneFormat) and read back with the same format;
 // the last matching line wins, other lines are skipped.
 constexpr const char *kTuneFormat =
     "{\"d\": %d, \"bc\": %d, \"M\": [%lld, %lld, %lld], \"kernel\": %d, \"zchunk\": %d, "
-    "\"depth2\": %d, \"ms_per_step\": %lf}";
+    "\"depth2\": %d, \"tb3\": %d, \"tb2\": %d, \"ms_per_step\": %lf}";
 
 void load_tuning(ace_solver *s)
 {
@@ -540,16 +581,19 @@ void load_tuning(ace_solver *s)
     if (!f) return;
     char line[512];
     while (fgets(line, sizeof line, f)) {
-        int d, bc, k, zc, k2;
+        int d, bc, k, zc, k2, v3, v2;
         long long m0, m1, m2;
         double ms;
-        if (sscanf(line, kTuneFormat, &d, &bc, &m0, &m1, &m2, &k, &zc, &k2, &ms) != 9) continue;
+        if (sscanf(line, kTuneFormat, &d, &bc, &m0, &m1, &m2, &k, &zc, &k2, &v3, &v2, &ms) != 11) continue;
         if (d == s->p.d && bc == s->p.bc && m0 == s->p.M[0] && m1 == s->p.M[1] && m2 == s->p.M[2] &&
             k >= ACE_KERNEL_DIRECT && k <= ACE_KERNEL_TBLOCK &&
-            (zc == 0 || zc >= TBLOCK_MIN_ZCHUNK) && k2 >= 1 && k2 <= tblock2d_max_depth()) {
+            (zc == 0 || zc >= TBLOCK_MIN_ZCHUNK) && k2 >= 1 && k2 <= tblock2d_max_depth() && v3 >= -1 &&
+            v3 < TB3_VARIANTS && v2 >= -1 && v2 < TB2_VARIANTS) {
             s->tuned_kernel = k;
             s->zchunk = zc;
             s->depth2 = k2;
+            s->tb3 = v3;
+            s->tb2 = v2;
         }
     }
     fclose(f);
@@ -749,12 +793,62 @@ int ace_set_kernel(ace_solver *s, int kernel, int depth)
 {
     if (!s || kernel < ACE_KERNEL_AUTO || kernel > ACE_KERNEL_TBLOCK || depth < 0) return ACE_E_ARG;
     if (kernel == ACE_KERNEL_TBLOCK && depth != 0) {
-        if (s->p.d == 3 && depth != 2) return ACE_E_ARG;
+        if (s->p.d == 3 && (depth < 2 || depth > 4)) return ACE_E_ARG;
         if (s->p.d == 2 && depth > tblock2d_max_depth()) return ACE_E_ARG;
         if (s->p.d == 2) s->depth2 = depth;
+        if (s->p.d == 3) s->tb3 = (depth == 2) ? -1 : (depth == 3 ? TB3_DEFAULT_DEPTH3 : TB3_DEFAULT_DEPTH4);
     }
     s->kernel = kernel;
     s->depth = depth;
+    return ACE_OK;
+}
+
+int ace_set_region3d(ace_solver *s, int depth, int rows, int rows_per_thread)
+{
+    if (!s || s->p.d != 3) return ACE_E_ARG;
+    if (depth == 2 && rows == 0 && rows_per_thread == 0) {
+        s->tb3 = -1;
+        return ACE_OK;
+    }
+    const int v = tb3_find(depth, rows, rows_per_thread);
+    if (v < 0) return ACE_E_ARG;
+    s->tb3 = v;
+    return ACE_OK;
+}
+
+int ace_get_region3d(const ace_solver *s, int *depth, int *rows, int *rows_per_thread)
+{
+    if (!s || !depth || !rows || !rows_per_thread || s->p.d != 3) return ACE_E_ARG;
+    if (s->tb3 < 0) {
+        *depth = 2;
+        *rows = 0;
+        *rows_per_thread = 0;
+    } else {
+        *depth = TB3_TABLE[s->tb3].depth;
+        *rows = TB3_TABLE[s->tb3].rows;
+        *rows_per_thread = TB3_TABLE[s->tb3].rpt;
+    }
+    return ACE_OK;
+}
+
+int ace_set_region2d(ace_solver *s, int rows, int rows_per_thread)
+{
+    if (!s || s->p.d != 2) return ACE_E_ARG;
+    if (rows == 0 && rows_per_thread == 0) {
+        s->tb2 = -1;
+        return ACE_OK;
+    }
+    const int v = tb2_find(rows, rows_per_thread);
+    if (v < 0) return ACE_E_ARG;
+    s->tb2 = v;
+    return ACE_OK;
+}
+
+int ace_get_region2d(const ace_solver *s, int *rows, int *rows_per_thread)
+{
+    if (!s || !rows || !rows_per_thread || s->p.d != 2) return ACE_E_ARG;
+    *rows = s->tb2 >= 0 ? TB2_TABLE[s->tb2].rows : 0;
+    *rows_per_thread = s->tb2 >= 0 ? TB2_TABLE[s->tb2].rpt : 0;
     return ACE_OK;
 }
 
@@ -965,24 +1059,35 @@ int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap)
 {
     if (!s || trial_steps < 1) return ACE_E_ARG;
     struct Cand {
-        int kernel, zchunk, depth2;
+        int kernel, zchunk, depth2, tb3, tb2;
     };
     std::vector<Cand> cands;
-    cands.push_back({ACE_KERNEL_DIRECT, s->zchunk, s->depth2});
-    if (s->p.total <= RESIDENT_MAX) cands.push_back({ACE_KERNEL_RESIDENT, s->zchunk, s->depth2});
-    if (march_supported(s->shape)) cands.push_back({ACE_KERNEL_MARCH, s->zchunk, s->depth2});
+    const int z0c = s->zchunk, k0 = s->depth2, v30 = s->tb3, v20 = s->tb2;
+    cands.push_back({ACE_KERNEL_DIRECT, z0c, k0, v30, v20});
+    if (s->p.total <= RESIDENT_MAX) cands.push_back({ACE_KERNEL_RESIDENT, z0c, k0, v30, v20});
+    if (march_supported(s->shape)) cands.push_back({ACE_KERNEL_MARCH, z0c, k0, v30, v20});
     if (s->p.d == 3 && tblock_supported(s->shape))
         for (int zc : {0, 16, 24, 32, 40, 48, 64, 128})  // 0: persistent grid
-            if (zc <= std::max<int64_t>(s->shape.M0, 16)) cands.push_back({ACE_KERNEL_TBLOCK, zc, s->depth2});
-    if (s->p.d == 2 && tblock2d_supported(s->shape))
+            if (zc <= std::max<int64_t>(s->shape.M0, 16)) cands.push_back({ACE_KERNEL_TBLOCK, zc, k0, -1, v20});
+    // the configurable 3D kernel: every depth and region shape, fewer plane chunks
+    if (s->p.d == 3 && tb3_supported(s->shape))
+        for (int v = 0; v < TB3_VARIANTS; ++v)
+            for (int zc : {0, 16, 32, 64})
+                if (zc <= std::max<int64_t>(s->shape.M0, 16)) cands.push_back({ACE_KERNEL_TBLOCK, zc, k0, v, v20});
+    if (s->p.d == 2 && tblock2d_supported(s->shape)) {
         for (int k2 : {1, 2, 3, 4, 5, 6, 8, 10, 12})
-            if (k2 <= tblock2d_max_depth()) cands.push_back({ACE_KERNEL_TBLOCK, s->zchunk, k2});
+            if (k2 <= tblock2d_max_depth()) cands.push_back({ACE_KERNEL_TBLOCK, z0c, k2, v30, -1});
+        // the register-resident 2D kernel: every region shape and depth
+        for (int v = 0; v < (tb2_supported(s->shape) ? TB2_VARIANTS : 0); ++v)
+            for (int k2 : {2, 3, 4, 5, 6, 8, 10, 12})
+                if (k2 <= tb2_max_depth(v)) cands.push_back({ACE_KERNEL_TBLOCK, z0c, k2, v30, v});
+    }
     const int64_t total = s->p.total;
     double *save = nullptr;
     ACE_HIP(hipMalloc((void **)&save, sizeof(double) * total));
     const int cur0 = s->cur;
     const int64_t steps0 = s->steps;
-    const int kernel0 = s->kernel, zchunk0 = s->zchunk, depth20 = s->depth2;
+    const int kernel0 = s->kernel, zchunk0 = s->zchunk, depth20 = s->depth2, tb30 = s->tb3, tb20 = s->tb2;
     int rc = hip_status(hipMemcpyAsync(save, s->buf[cur0], sizeof(double) * total,
                                        hipMemcpyDeviceToDevice, s->stream));
     auto restore = [&]() {
@@ -1013,6 +1118,8 @@ int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap)
         s->kernel = c.kernel;
         s->zchunk = c.zchunk;
         s->depth2 = c.depth2;
+        s->tb3 = c.tb3;
+        s->tb2 = c.tb2;
         // Each length is run once untimed (code object load, graph capture)
         // and then timed.  A trial shorter than kMinTrialMs is lengthened to
         // about that, so small fields are timed in the steady state of a long
@@ -1028,11 +1135,16 @@ int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap)
             if ((rc = time_run(steps, &ms)) < 0) break;
         }
         const double per = ms / (double)steps;
-        char buf[240];
+        char buf[320];
+        const int d3 = c.tb3 >= 0 ? TB3_TABLE[c.tb3].depth : 2;
+        const int r3 = c.tb3 >= 0 ? TB3_TABLE[c.tb3].rows : 0, t3 = c.tb3 >= 0 ? TB3_TABLE[c.tb3].rpt : 0;
+        const int r2 = c.tb2 >= 0 ? TB2_TABLE[c.tb2].rows : 0, t2 = c.tb2 >= 0 ? TB2_TABLE[c.tb2].rpt : 0;
         snprintf(buf, sizeof buf,
-                 "%s{\"kernel\": %d, \"zchunk\": %d, \"depth2\": %d, \"steps\": %lld, "
-                 "\"ms_per_step\": %.6f}",
-                 first ? "" : ", ", c.kernel, c.zchunk, c.depth2, (long long)steps, per);
+                 "%s{\"kernel\": %d, \"zchunk\": %d, \"depth2\": %d, \"tb3\": %d, \"depth3\": %d, "
+                 "\"rows\": %d, \"rows_per_thread\": %d, \"tb2\": %d, \"rows2\": %d, "
+                 "\"rows_per_thread2\": %d, \"steps\": %lld, \"ms_per_step\": %.6f}",
+                 first ? "" : ", ", c.kernel, c.zchunk, c.depth2, c.tb3, d3, r3, t3, c.tb2, r2, t2, (long long)steps,
+                 per);
         rec += buf;
         first = false;
         if (per < best_ms) {
@@ -1045,6 +1157,8 @@ int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap)
     s->kernel = kernel0;
     s->zchunk = zchunk0;
     s->depth2 = depth20;
+    s->tb3 = tb30;
+    s->tb2 = tb20;
     if (rc >= 0) rc = restore();
     if (rc >= 0) rc = hip_status(hipStreamSynchronize(s->stream));
     (void)hipFree(save);
@@ -1053,19 +1167,30 @@ int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap)
     s->tuned_kernel = best.kernel;
     s->zchunk = best.zchunk;
     s->depth2 = best.depth2;
+    s->tb3 = best.tb3;
+    s->tb2 = best.tb2;
     drop_graphs(s);
-    char buf[200];
-    snprintf(buf, sizeof buf,
-             "], \"choice\": {\"kernel\": %d, \"zchunk\": %d, \"depth2\": %d, \"ms_per_step\": %.6f}}",
-             best.kernel, best.zchunk, best.depth2, best_ms);
+    char buf[320];
+    {
+        const int d3 = best.tb3 >= 0 ? TB3_TABLE[best.tb3].depth : 2;
+        const int r3 = best.tb3 >= 0 ? TB3_TABLE[best.tb3].rows : 0;
+        const int t3 = best.tb3 >= 0 ? TB3_TABLE[best.tb3].rpt : 0;
+        const int r2 = best.tb2 >= 0 ? TB2_TABLE[best.tb2].rows : 0;
+        const int t2 = best.tb2 >= 0 ? TB2_TABLE[best.tb2].rpt : 0;
+        snprintf(buf, sizeof buf,
+                 "], \"choice\": {\"kernel\": %d, \"zchunk\": %d, \"depth2\": %d, \"tb3\": %d, "
+                 "\"depth3\": %d, \"rows\": %d, \"rows_per_thread\": %d, \"tb2\": %d, \"rows2\": %d, "
+                 "\"rows_per_thread2\": %d, \"ms_per_step\": %.6f}}",
+                 best.kernel, best.zchunk, best.depth2, best.tb3, d3, r3, t3, best.tb2, r2, t2, best_ms);
+    }
     rec += buf;
     if (json && cap > 0) snprintf(json, cap, "%s", rec.c_str());
     if (log_enabled())
         fprintf(stderr,
                 "[ace] autotune d=%d bc=%d M=%lldx%lldx%lld: kernel %d, plane chunk %d, 2D depth %d, "
-                "%.6f ms/step\n",
+                "3D variant %d, 2D variant %d, %.6f ms/step\n",
                 s->p.d, s->p.bc, (long long)s->p.M[0], (long long)s->p.M[1], (long long)s->p.M[2], best.kernel,
-                best.zchunk, best.depth2, best_ms);
+                best.zchunk, best.depth2, best.tb3, best.tb2, best_ms);
     const char *path = getenv("ACE_AUTOTUNE_CACHE");
     if (path) {
         FILE *f = fopen(path, "a");
@@ -1073,9 +1198,9 @@ int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap)
             // the same fields as kTuneFormat, ms written with a fixed precision
             fprintf(f,
                     "{\"d\": %d, \"bc\": %d, \"M\": [%lld, %lld, %lld], \"kernel\": %d, \"zchunk\": %d, "
-                    "\"depth2\": %d, \"ms_per_step\": %.6f}\n",
+                    "\"depth2\": %d, \"tb3\": %d, \"tb2\": %d, \"ms_per_step\": %.6f}\n",
                     s->p.d, s->p.bc, (long long)s->p.M[0], (long long)s->p.M[1], (long long)s->p.M[2],
-                    best.kernel, best.zchunk, best.depth2, best_ms);
+                    best.kernel, best.zchunk, best.depth2, best.tb3, best.tb2, best_ms);
             fclose(f);
         }
     }
@@ -1163,10 +1288,11 @@ int ace_backward(ace_solver *s, const double *lambdaT, double *dphi0, double *de
         ACE_HIP(hipStreamWaitEvent(s->aux, s->ev_rev[b], 0));
         ACE_HIP(hipMemcpyAsync(seg, s->ckpt + j * total, bytes, hipMemcpyDeviceToDevice, s->aux));
         if (blocked2d) {
+            const int per = steps_per_launch_of(s, ACE_KERNEL_TBLOCK);
             for (int64_t i = 0; i < n;) {  // each launch writes its K intermediate states
-                const int K = (int)std::min<int64_t>(s->depth2, n - i);
-                ACE_HIP(launch_step_tblock2d(s->shape, s->coef, seg + i * total, seg + (i + 1) * total,
-                                             nullptr, nullptr, K, total, s->aux));
+                const int K = (int)std::min<int64_t>(per, n - i);
+                ACE_HIP(launch_blocked2d(s, seg + i * total, seg + (i + 1) * total, nullptr, nullptr, K, total,
+                                         s->aux));
                 i += K;
             }
         } else {

@@ -84,6 +84,24 @@ bool tblock_supported(const Shape &s);
 int64_t tblock_partials_needed(const Shape &s, int zchunk);
 constexpr int TBLOCK_MIN_ZCHUNK = 8;
 
+// 3D: the configurable temporally blocked kernel (ace_tb3.h).  Variant v of
+// TB3_TABLE advances `depth` steps per launch on regions of `rows` x 64
+// nodes with `rpt` rows per thread (rows / rpt wavefronts per workgroup).
+// Same partials contract (the monitors are those of the input field) and
+// the same zchunk meaning as launch_step_tblock2.
+struct Tb3Variant {
+    int depth, rows, rpt;
+};
+constexpr int TB3_VARIANTS = 6;
+constexpr Tb3Variant TB3_TABLE[TB3_VARIANTS] = {{2, 32, 4}, {3, 48, 3}, {3, 48, 4},
+                                                {3, 32, 2}, {4, 32, 4}, {4, 32, 2}};
+constexpr int TB3_DEFAULT_DEPTH3 = 1, TB3_DEFAULT_DEPTH4 = 5;  // variants ace_set_kernel picks
+hipError_t launch_step_tb3(int v, const Shape &s, const StepCoef &c, const double *in, double *out,
+                           double *partials, int64_t *nparts, int zchunk, hipStream_t st);
+int64_t tb3_partials_needed(int v, const Shape &s, int zchunk);
+bool tb3_supported(const Shape &s);  // d == 3 with planes of fewer than 2^31 nodes
+int tb3_find(int depth, int rows, int rpt);  // variant index, or -1
+
 // 2D: K steps per launch on LDS regions (1 <= K <= tblock2d_max_depth()).
 // With level_stride > 0 every intermediate level k = 1..K is written to
 // out + (k-1) * level_stride (the adjoint's segment recompute); otherwise only
@@ -91,6 +109,22 @@ constexpr int TBLOCK_MIN_ZCHUNK = 8;
 hipError_t launch_step_tblock2d(const Shape &s, const StepCoef &c, const double *in,
                                 double *out, double *partials, int64_t *nparts, int K,
                                 int64_t level_stride, hipStream_t st);
+// 2D: the register-resident blocked kernel (ace_tb2.h).  Variant v of
+// TB2_TABLE works on regions of `rows` x 64 nodes with `rpt` rows per thread
+// and takes 1 <= K <= rows / 2 - 4 steps per launch; same contracts as
+// launch_step_tblock2d.
+struct Tb2Variant {
+    int rows, rpt;
+};
+constexpr int TB2_VARIANTS = 4;
+constexpr Tb2Variant TB2_TABLE[TB2_VARIANTS] = {{32, 4}, {32, 2}, {64, 4}, {16, 2}};
+hipError_t launch_step_tb2(int v, const Shape &s, const StepCoef &c, const double *in, double *out,
+                           double *partials, int64_t *nparts, int K, int64_t level_stride, hipStream_t st);
+int64_t tb2_blocks(int v, const Shape &s, int K);
+inline int tb2_max_depth(int v) { return TB2_TABLE[v].rows / 2 - 4; }
+int tb2_find(int rows, int rpt);  // variant index, or -1
+bool tb2_supported(const Shape &s);  // d == 2 with fewer than 2^31 nodes
+
 // K transposed steps: states[i * stride] = phi^{m+i}, i = 0..K; lam_in =
 // lambda^{m+K}; writes lambda^m and one partial of dL/dkappa per block.
 hipError_t launch_adjoint_tblock2d(const Shape &s, const StepCoef &c, const double *lam_in,

@@ -22,11 +22,15 @@
 // starts on 256 bytes and the arrays do not start on the same HBM channel).
 // Any step reads each node's 2d+1 populations and writes them: at least
 // 16 (2d+1) bytes of HBM per node update, against 16 for the FD step.
-// Three kernels compute the same result bit for bit: one thread per node
+// The new populations depend on the old ones only through phi.  Four launch
+// forms compute the same result bit for bit: one thread per node
 // (k_pop_direct); a tiled march on cache-line-aligned tiles that sums phi
 // from the populations itself (k_pop_update, fused: 16 (2d+1) bytes per node
-// update); and the split form, a streaming moment pass (k_pop_moment) then
-// the same tiled update reading phi (16 (2d+1) + 16 bytes).
+// update); the split form, a streaming moment pass (k_pop_moment) then the
+// same tiled update reading phi (16 (2d+1) + 16 bytes); and the carried
+// form, in which each update also writes phi of its new populations (summed
+// in the same order as every moment here, so it equals a moment pass bit
+// for bit) and the next update reads only that (8 (2d+1) + 16 bytes).
 #include <math.h>
 #include <string.h>
 
@@ -164,11 +168,12 @@ using PopTileDefault = PopTile<128, 4, 4>;  // 16 x 128, 512 threads
 
 // FUSED: `src` holds the populations and phi of every node the tile needs is
 // summed here from its 2d+1 arrays (k = 0..2d in order, as everywhere);
-// otherwise `src` is phi (written by k_pop_moment).
-template <class T, int D, int BC, int RV, bool FUSED>
+// otherwise `src` is phi (written by k_pop_moment or carried).  CARRY: phi of
+// the new populations (k = 0..2d in order) also goes to phi_out.
+template <class T, int D, int BC, int RV, bool FUSED, bool CARRY>
 __global__ __launch_bounds__(T::UNT) void k_pop_update(Shape s, PopCoef c, const double *__restrict__ src,
-                                                       double *__restrict__ fout, int tiles_x, int tiles_y,
-                                                       int zchunk)
+                                                       double *__restrict__ fout, double *__restrict__ phi_out,
+                                                       int tiles_x, int tiles_y, int zchunk)
 {
     constexpr int UX = T::UX, URYT = T::URYT, UOY = T::UOY, ULW = T::ULW, ULH = T::ULH,
                   ULP = T::ULP, URING = T::URING, URPT = T::URPT, UNT = T::UNT;
@@ -299,6 +304,13 @@ __global__ __launch_bounds__(T::UNT) void k_pop_update(Shape s, PopCoef c, const
             // inputs in L2
 #pragma unroll
             for (int k = 0; k < Q; ++k) __builtin_nontemporal_store(outv[r][k], fout + k * c.ps + o);
+            if (CARRY) {
+                // the zeroth moment of the new populations, in the order of phi_at
+                double v = outv[r][0];
+#pragma unroll
+                for (int k = 1; k < Q; ++k) v += outv[r][k];
+                phi_out[o] = v;
+            }
         }
     };
 
@@ -377,10 +389,12 @@ __global__ void k_pop_equilibrium(int q, int64_t ps, int64_t n, double w0, doubl
 constexpr int POP_ZCHUNK = 128;  // planes per workgroup in 3D
 
 // mode: 0 one thread per node; 1 tiled, phi summed in the tile (fused);
-// 2 split: k_pop_moment writes phi to `phi`, then the tiled update reads it.
+// 2 split: k_pop_moment writes phi to `phi`, then the tiled update reads it;
+// 3 carried: the tiled update reads phi from `phi` and writes phi of the new
+// populations to phi_next.
 template <int D, int BC, int RV>
 hipError_t launch_pop_t(const Shape &s, const PopCoef &c, const double *fin, double *fout, int mode,
-                        double *phi, hipStream_t st)
+                        double *phi, double *phi_next, hipStream_t st)
 {
     const int64_t n = s.M0 * s.M1 * s.M2;
     if (mode == 0 || D == 1) {
@@ -395,13 +409,16 @@ hipError_t launch_pop_t(const Shape &s, const PopCoef &c, const double *fin, dou
         const int uty = (int)((s.M1 + T::UOY - 1) / T::UOY);
         const int64_t ublk = (int64_t)utx * uty * chunks;
         if (mode == 1) {
-            hipLaunchKernelGGL((k_pop_update<T, D, BC, RV, true>), dim3((unsigned)ublk), dim3(T::UNT), 0, st,
-                               s, c, fin, fout, utx, uty, POP_ZCHUNK);
+            hipLaunchKernelGGL((k_pop_update<T, D, BC, RV, true, false>), dim3((unsigned)ublk), dim3(T::UNT), 0,
+                               st, s, c, fin, fout, nullptr, utx, uty, POP_ZCHUNK);
+        } else if (mode == 3) {
+            hipLaunchKernelGGL((k_pop_update<T, D, BC, RV, false, true>), dim3((unsigned)ublk), dim3(T::UNT), 0,
+                               st, s, c, phi, fout, phi_next, utx, uty, POP_ZCHUNK);
         } else {
             hipLaunchKernelGGL(k_pop_moment, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, 2 * D + 1,
                                c.ps, n, fin, phi);
-            hipLaunchKernelGGL((k_pop_update<T, D, BC, RV, false>), dim3((unsigned)ublk), dim3(T::UNT), 0, st,
-                               s, c, phi, fout, utx, uty, POP_ZCHUNK);
+            hipLaunchKernelGGL((k_pop_update<T, D, BC, RV, false, false>), dim3((unsigned)ublk), dim3(T::UNT), 0,
+                               st, s, c, phi, fout, nullptr, utx, uty, POP_ZCHUNK);
         }
     }
     return hipGetLastError();
@@ -409,37 +426,37 @@ hipError_t launch_pop_t(const Shape &s, const PopCoef &c, const double *fin, dou
 
 template <int D, int BC>
 hipError_t launch_pop_nit(const Shape &s, const PopCoef &c, const double *fin, double *fout, int mode,
-                          double *phi, hipStream_t st)
+                          double *phi, double *phi_next, hipStream_t st)
 {
     switch (root_variant(c.sc)) {
-    case 1: return launch_pop_t<D, BC, 1>(s, c, fin, fout, mode, phi, st);
-    case 2: return launch_pop_t<D, BC, 2>(s, c, fin, fout, mode, phi, st);
-    case 3: return launch_pop_t<D, BC, 3>(s, c, fin, fout, mode, phi, st);
-    case 5: return launch_pop_t<D, BC, 5>(s, c, fin, fout, mode, phi, st);
-    case 6: return launch_pop_t<D, BC, 6>(s, c, fin, fout, mode, phi, st);
-    default: return launch_pop_t<D, BC, 0>(s, c, fin, fout, mode, phi, st);
+    case 1: return launch_pop_t<D, BC, 1>(s, c, fin, fout, mode, phi, phi_next, st);
+    case 2: return launch_pop_t<D, BC, 2>(s, c, fin, fout, mode, phi, phi_next, st);
+    case 3: return launch_pop_t<D, BC, 3>(s, c, fin, fout, mode, phi, phi_next, st);
+    case 5: return launch_pop_t<D, BC, 5>(s, c, fin, fout, mode, phi, phi_next, st);
+    case 6: return launch_pop_t<D, BC, 6>(s, c, fin, fout, mode, phi, phi_next, st);
+    default: return launch_pop_t<D, BC, 0>(s, c, fin, fout, mode, phi, phi_next, st);
     }
 }
 
 template <int D>
 hipError_t launch_pop_bc(const Shape &s, const PopCoef &c, const double *fin, double *fout, int mode,
-                         double *phi, hipStream_t st)
+                         double *phi, double *phi_next, hipStream_t st)
 {
     switch (s.bc) {
-    case BC_HN: return launch_pop_nit<D, BC_HN>(s, c, fin, fout, mode, phi, st);
-    case BC_HD: return launch_pop_nit<D, BC_HD>(s, c, fin, fout, mode, phi, st);
-    case BC_P: return launch_pop_nit<D, BC_P>(s, c, fin, fout, mode, phi, st);
+    case BC_HN: return launch_pop_nit<D, BC_HN>(s, c, fin, fout, mode, phi, phi_next, st);
+    case BC_HD: return launch_pop_nit<D, BC_HD>(s, c, fin, fout, mode, phi, phi_next, st);
+    case BC_P: return launch_pop_nit<D, BC_P>(s, c, fin, fout, mode, phi, phi_next, st);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_pop_step(const Shape &s, const PopCoef &c, const double *fin, double *fout, int mode,
-                           double *phi, hipStream_t st)
+                           double *phi, double *phi_next, hipStream_t st)
 {
     switch (s.d) {
-    case 1: return launch_pop_bc<1>(s, c, fin, fout, mode, phi, st);
-    case 2: return launch_pop_bc<2>(s, c, fin, fout, mode, phi, st);
-    case 3: return launch_pop_bc<3>(s, c, fin, fout, mode, phi, st);
+    case 1: return launch_pop_bc<1>(s, c, fin, fout, mode, phi, phi_next, st);
+    case 2: return launch_pop_bc<2>(s, c, fin, fout, mode, phi, phi_next, st);
+    case 3: return launch_pop_bc<3>(s, c, fin, fout, mode, phi, phi_next, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -458,6 +475,10 @@ struct ace_pop {
     double *f[2] = {nullptr, nullptr};
     double *phi = nullptr;  // zeroth moment / staging of phi0
     int cur = 0;
+    // carried form: phi of f[cur] in carry[ccur] while carry_ok
+    double *carry[2] = {nullptr, nullptr};
+    int ccur = 0;
+    int carry_ok = 0;
     int kernel = ACE_POP_AUTO;
     hipStream_t stream = nullptr;
     int64_t steps = 0;
@@ -470,7 +491,8 @@ int pop_mode(const ace_pop *P)
 {
     if (P->p.d == 1 || P->kernel == ACE_POP_DIRECT) return 0;
     if (P->kernel == ACE_POP_SPLIT) return 2;
-    return 1;  // fused (also the automatic choice for d >= 2)
+    if (P->kernel == ACE_POP_FUSED) return 1;
+    return 3;  // carried (also the automatic choice for d >= 2)
 }
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -507,6 +529,8 @@ int ace_pop_create(int d, const int64_t *N, const double *L, const double *R, do
     hipError_t e = hipMalloc((void **)&P->f[0], bytes);
     if (e == hipSuccess) e = hipMalloc((void **)&P->f[1], bytes);
     if (e == hipSuccess) e = hipMalloc((void **)&P->phi, sizeof(double) * (size_t)p.total);
+    for (int b = 0; b < 2 && e == hipSuccess && d >= 2; ++b)
+        e = hipMalloc((void **)&P->carry[b], sizeof(double) * (size_t)p.total);
     if (e != hipSuccess) {
         ace_pop_destroy(P);
         return hip_status(e);
@@ -521,6 +545,8 @@ int ace_pop_destroy(ace_pop *P)
     if (P->f[0]) (void)hipFree(P->f[0]);
     if (P->f[1]) (void)hipFree(P->f[1]);
     if (P->phi) (void)hipFree(P->phi);
+    for (double *b : P->carry)
+        if (b) (void)hipFree(b);
     delete P;
     return ACE_OK;
 }
@@ -536,7 +562,8 @@ int ace_pop_info(const ace_pop *P, int64_t M[3], int64_t *total, int *q, double 
     if (omega1) *omega1 = P->omega1;
     if (s) *s = P->s;
     if (device_bytes)
-        *device_bytes = (int64_t)sizeof(double) * (2 * (int64_t)P->q * P->c.ps + P->p.total);
+        *device_bytes = (int64_t)sizeof(double) *
+                        (2 * (int64_t)P->q * P->c.ps + P->p.total * (P->carry[0] ? 3 : 1));
     return ACE_OK;
 }
 
@@ -549,7 +576,7 @@ int ace_pop_set_stream(ace_pop *P, void *st)
 
 int ace_pop_set_kernel(ace_pop *P, int kernel)
 {
-    if (!P || kernel < ACE_POP_AUTO || kernel > ACE_POP_SPLIT) return ACE_E_ARG;
+    if (!P || kernel < ACE_POP_AUTO || kernel > ACE_POP_CARRY) return ACE_E_ARG;
     P->kernel = kernel;
     return ACE_OK;
 }
@@ -572,6 +599,7 @@ int ace_pop_set_phi0(ace_pop *P, const double *phi0, int where)
     hipLaunchKernelGGL(k_pop_equilibrium, dim3(blocks_for(n)), dim3(256), 0, P->stream, P->q, P->c.ps, n,
                        P->c.w0, P->c.w1, P->phi, P->f[P->cur]);
     P->steps = 0;
+    P->carry_ok = 0;
     return hip_status(hipGetLastError());
 }
 
@@ -585,6 +613,7 @@ int ace_pop_set_populations(ace_pop *P, const double *f, int where)
                                     P->stream);
     if (e == hipSuccess && where == ACE_HOST) e = hipStreamSynchronize(P->stream);
     P->steps = 0;
+    P->carry_ok = 0;
     return hip_status(e);
 }
 
@@ -604,13 +633,24 @@ int ace_pop_step(ace_pop *P, int64_t nsteps)
 {
     if (!P || nsteps < 0) return ACE_E_ARG;
     const int mode = pop_mode(P);
+    if (nsteps > 0 && mode == 3 && !P->carry_ok) {  // phi of the current populations, once
+        const int64_t n = P->p.total;
+        hipLaunchKernelGGL(k_pop_moment, dim3(blocks_for(n)), dim3(256), 0, P->stream, P->q, P->c.ps, n,
+                           P->f[P->cur], P->carry[P->ccur]);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_status(e);
+        P->carry_ok = 1;
+    }
     for (int64_t t = 0; t < nsteps; ++t) {
-        hipError_t e = launch_pop_step(P->shape, P->c, P->f[P->cur], P->f[P->cur ^ 1], mode, P->phi,
-                                       P->stream);
+        hipError_t e = launch_pop_step(P->shape, P->c, P->f[P->cur], P->f[P->cur ^ 1], mode,
+                                       mode == 3 ? P->carry[P->ccur] : P->phi,
+                                       mode == 3 ? P->carry[P->ccur ^ 1] : nullptr, P->stream);
         if (e != hipSuccess) return hip_status(e);
         P->cur ^= 1;
+        if (mode == 3) P->ccur ^= 1;
         ++P->steps;
     }
+    if (nsteps > 0 && mode != 3) P->carry_ok = 0;
     return ACE_OK;
 }
 

@@ -1,0 +1,212 @@
+// 2D temporal blocking with the region held in registers: K steps of the
+// scheme per launch (1 <= K <= the region's depth limit).
+//
+// A workgroup of TRW wavefronts loads the RH x 64 region (RH = TRW * RYT)
+// around an (RH - 2K) x (64 - 2K) output tile, a ring of K nodes recomputed
+// instead of exchanged.  Lane x of wavefront w holds the RYT consecutive
+// region rows w RYT .. w RYT + RYT - 1 of column x in registers and advances
+// them K times.  Per level the neighbours of a node are:
+//   * along the row (i2): the neighbouring lanes' registers, moved by DPP
+//     lane shifts (the lanes at the region's edge receive 0; they are ring
+//     nodes, never needed at the next level);
+//   * across rows (i1): the thread's own registers, except above its first
+//     and below its last row, which come from the neighbouring wavefronts
+//     through two LDS edge rows per wavefront, double-buffered by level
+//     parity (one workgroup barrier per level).
+// After level k only region rows k .. RH-1-k are still needed, so the rows
+// outside are skipped (wave-uniform tests).  Values outside the domain are
+// loaded BC-mapped (clamped / zero / wrapped); for Neumann and Dirichlet a
+// boundary node's outward neighbour is the node itself or 0 (the ring values
+// outside the domain are only right at level 0).  The arithmetic and the
+// neighbour order are those of the one-step kernels, so the result equals K
+// one-step launches bit for bit.  Monitors (MON) are those of the input
+// field; LEVELS writes every level k to out + (k - 1) * level_stride (the
+// adjoint's segment recompute).
+#pragma once
+
+#include "ace_device.h"
+
+namespace ace {
+namespace tb2 {
+
+constexpr int RX = 64;  // region width: one wavefront
+
+template <int BC>
+__device__ __forceinline__ int64_t mapc(int64_t c, int64_t n)
+{
+    if (c >= 0 && c < n) return c;
+    if (BC == BC_HN) return c < 0 ? 0 : n - 1;
+    if (BC == BC_HD) return -1;
+    const int64_t r = c % n;  // the ring may wrap more than once on tiny grids
+    return r < 0 ? r + n : r;
+}
+
+// The next lower lane's value (CTRL 0x138, DPP wave_shr:1) or the next higher
+// lane's (0x130, wave_shl:1); lane 0 (resp. 63) receives 0.
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double v)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u & 0xffffffffull), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+template <int TRW, int RYT>
+struct Geom {
+    static constexpr int NT = RX * TRW;
+    static constexpr int RH = TRW * RYT;
+    static constexpr int KMAX = RH / 2 - 4;  // keeps an (RH - 2 KMAX = 8) x (64 - 2 KMAX) tile
+};
+
+template <int BC, bool MON, bool LEVELS, int RV, int TRW, int RYT>
+__global__ __launch_bounds__(RX * TRW) void k_tb2(Shape s, StepCoef c, const double *__restrict__ in,
+                                                  double *__restrict__ out, double *__restrict__ partials,
+                                                  int K, int tiles_x, int64_t level_stride)
+{
+    using G = Geom<TRW, RYT>;
+    constexpr int NT = G::NT, RH = G::RH;
+    __shared__ double EB[2 * 2 * TRW * RX];  // [parity][top | bottom][wavefront][lane]
+    __shared__ double red[3 * (NT / 64)];
+    const int tx = threadIdx.x & (RX - 1);
+    const int tr = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront (uniform)
+    auto eb = [&](int par, int side, int w) -> double * { return EB + ((par * 2 + side) * TRW + w) * RX; };
+
+    const int oy = RH - 2 * K, ox = RX - 2 * K;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t yr0 = (tile / tiles_x) * oy - K;  // global row of region row 0
+    const int64_t xg = (tile % tiles_x) * ox - K + tx;
+    const int64_t mx = mapc<BC>(xg, s.M2);
+    const bool xin = xg >= 0 && xg < s.M2 && tx >= K && tx < RX - K;
+    const bool xb0 = (xg == 0), xb1 = (xg == s.M2 - 1);
+
+    // level 0, and per row: the output offset of a tile-interior node in the
+    // domain (-1 otherwise; also the monitor's node set) and the domain-edge
+    // flags (wave-uniform)
+    double v[RYT];
+    int oof[RYT];
+    bool yb0[RYT], yb1[RYT];
+#pragma unroll
+    for (int r = 0; r < RYT; ++r) {
+        const int ry = tr * RYT + r;
+        const int64_t yg = yr0 + ry;
+        const int64_t my = mapc<BC>(yg, s.M1);
+        v[r] = (my < 0 || mx < 0) ? 0.0 : in[my * s.M2 + mx];
+        oof[r] = (xin && ry >= K && ry < RH - K && yg >= 0 && yg < s.M1) ? (int)(yg * s.M2 + xg) : -1;
+        yb0[r] = (yg == 0);
+        yb1[r] = (yg == s.M1 - 1);
+    }
+    eb(0, 0, tr)[tx] = v[0];
+    eb(0, 1, tr)[tx] = v[RYT - 1];
+    __syncthreads();
+
+    MonAcc m;
+    mon_zero(m);
+    for (int k = 1; k <= K; ++k) {
+        const int rd = (k - 1) & 1;
+        double eT = 0.0, eB = 0.0;
+        if (tr > 0) eT = eb(rd, 1, tr - 1)[tx];
+        if (tr < TRW - 1) eB = eb(rd, 0, tr + 1)[tx];
+        double nv[RYT];
+#pragma unroll
+        for (int r = 0; r < RYT; ++r) {
+            nv[r] = v[r];
+            const int ry = tr * RYT + r;
+            if (ry < k || ry >= RH - k) continue;  // wave-uniform: a ring row of this level
+            const double p = v[r];
+            double ym = (r > 0) ? v[r > 0 ? r - 1 : 0] : eT;
+            double yp = (r < RYT - 1) ? v[r < RYT - 1 ? r + 1 : 0] : eB;
+            double xm = lane_shift<0x138>(p);
+            double xp = lane_shift<0x130>(p);
+            // (the monitor's nodes, the tile interior, are all level-1 rows)
+            if (MON && k == 1 && oof[r] >= 0) {
+                // next-node differences with the BC value past the end (the
+                // loaded ring holds it), plus Dirichlet's first-node wall edge
+                const double dy = yp - p, dx = xp - p;
+                double gr = fma(dy, dy, dx * dx);
+                if (BC == BC_HD) {
+                    if (yb0[r]) gr = fma(p, p, gr);
+                    if (xb0) gr = fma(p, p, gr);
+                }
+                m.bulk += bulk_term(p);
+                m.grad += gr;
+                m.mx = nan_max(m.mx, fabs(p));
+            }
+            if (BC != BC_P) {
+                const double wall = (BC == BC_HN) ? p : 0.0;
+                if (yb0[r]) ym = wall;
+                if (yb1[r]) yp = wall;
+                if (xb0) xm = wall;
+                if (xb1) xp = wall;
+            }
+            const double nsum = (ym + yp) + (xm + xp);
+            const double val = update_n<2, RV>(p, nsum, c);
+            nv[r] = val;
+            if ((LEVELS || k == K) && oof[r] >= 0)
+                out[(LEVELS ? (int64_t)(k - 1) * level_stride : 0) + oof[r]] = val;
+        }
+#pragma unroll
+        for (int r = 0; r < RYT; ++r) v[r] = nv[r];
+        if (k < K) {
+            eb(k & 1, 0, tr)[tx] = v[0];
+            eb(k & 1, 1, tr)[tx] = v[RYT - 1];
+            __syncthreads();
+        }
+    }
+    if (MON) block_reduce_store(m, red, partials + 3 * blockIdx.x);
+}
+
+template <int TRW, int RYT>
+void tiles(const Shape &s, int K, int &tiles_x, int &ntiles)
+{
+    const int oy = Geom<TRW, RYT>::RH - 2 * K, ox = RX - 2 * K;
+    tiles_x = (int)((s.M2 + ox - 1) / ox);
+    ntiles = tiles_x * (int)((s.M1 + oy - 1) / oy);
+}
+
+// Dispatch over the boundary condition, the output mode (monitor partials,
+// every level, last level) and the root variants.
+template <int TRW, int RYT>
+hipError_t launch_any(const Shape &s, const StepCoef &c, const double *in, double *out, double *partials,
+                      int64_t *nparts, int K, int64_t level_stride, hipStream_t st)
+{
+    using G = Geom<TRW, RYT>;
+    if (K < 1 || K > G::KMAX) return hipErrorInvalidValue;
+    int tiles_x, ntiles;
+    tiles<TRW, RYT>(s, K, tiles_x, ntiles);
+    if (nparts) *nparts = ntiles;
+    const bool levels = level_stride > 0;
+    const int rv = root_variant(c);
+    auto go = [&](auto BCc, auto RVc) {
+        constexpr int B = decltype(BCc)::value, R = decltype(RVc)::value;
+        if (partials)
+            hipLaunchKernelGGL((k_tb2<B, true, false, R, TRW, RYT>), dim3(ntiles), dim3(G::NT), 0, st, s, c, in,
+                               out, partials, K, tiles_x, level_stride);
+        else if (levels)
+            hipLaunchKernelGGL((k_tb2<B, false, true, R, TRW, RYT>), dim3(ntiles), dim3(G::NT), 0, st, s, c, in,
+                               out, partials, K, tiles_x, level_stride);
+        else
+            hipLaunchKernelGGL((k_tb2<B, false, false, R, TRW, RYT>), dim3(ntiles), dim3(G::NT), 0, st, s, c,
+                               in, out, partials, K, tiles_x, level_stride);
+        return hipGetLastError();
+    };
+    auto by_rv = [&](auto BCc) {
+        switch (rv) {
+        case 1: return go(BCc, std::integral_constant<int, 1>());
+        case 2: return go(BCc, std::integral_constant<int, 2>());
+        case 3: return go(BCc, std::integral_constant<int, 3>());
+        case 5: return go(BCc, std::integral_constant<int, 5>());
+        case 6: return go(BCc, std::integral_constant<int, 6>());
+        default: return go(BCc, std::integral_constant<int, 0>());
+        }
+    };
+    switch (s.bc) {
+    case BC_HN: return by_rv(std::integral_constant<int, BC_HN>());
+    case BC_HD: return by_rv(std::integral_constant<int, BC_HD>());
+    case BC_P: return by_rv(std::integral_constant<int, BC_P>());
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace tb2
+}  // namespace ace

@@ -202,7 +202,7 @@ def test_run_time_argument_errors(ace, orc):
     s3, p3 = _pair(ace, orc, 3, 12, 2)
     s2, p2 = _pair(ace, orc, 2, 40, 0)
     calls = [lambda: s3.step(-1), lambda: s3.run_monitored(10, 0),
-             lambda: s3.set_kernel(ace.ACE_KERNEL_TBLOCK, 3),
+             lambda: s3.set_kernel(ace.ACE_KERNEL_TBLOCK, 5),
              lambda: s3.set_kernel(9), lambda: s3.set_kernel(ace.ACE_KERNEL_DIRECT, -1),
              lambda: s2.set_kernel(ace.ACE_KERNEL_TBLOCK, 13), lambda: s2.set_plane_chunk(32)]
     for call in calls:

@@ -45,7 +45,7 @@ def test_populations_match_oracle(ace, orc, d, N, bc):
     f0 = p.pop_equilibrium(phi0) + rng.normal(0, 0.01, (2 * d + 1,) + p.shape)  # off equilibrium
     want = p.pop_run(f0, 9)
     got = {}
-    kernels = (ace.ACE_POP_DIRECT, ace.ACE_POP_FUSED, ace.ACE_POP_SPLIT, ace.ACE_POP_AUTO)
+    kernels = (ace.ACE_POP_DIRECT, ace.ACE_POP_FUSED, ace.ACE_POP_SPLIT, ace.ACE_POP_CARRY, ace.ACE_POP_AUTO)
     for kernel in kernels:
         g = ace.Pop(*args)
         assert g.shape == p.shape and g.q == 2 * d + 1
@@ -60,6 +60,22 @@ def test_populations_match_oracle(ace, orc, d, N, bc):
         g.close()
     for kernel in kernels[1:]:
         assert np.array_equal(got[ace.ACE_POP_DIRECT], got[kernel]), kernel
+    # kernels switched between steps: the carried phi is rebuilt after
+    # another kernel's step, after new populations, and survives get_phi
+    g = ace.Pop(*args)
+    g.set_kernel(ace.ACE_POP_CARRY)
+    g.set_populations(f0)
+    g.step(4)
+    g.get_phi()
+    g.set_kernel(ace.ACE_POP_FUSED)
+    g.step(2)
+    g.set_kernel(ace.ACE_POP_CARRY)
+    g.step(3)
+    assert np.array_equal(g.get_populations(), got[ace.ACE_POP_DIRECT])
+    g.set_populations(f0)
+    g.step(9)
+    assert np.array_equal(g.get_populations(), got[ace.ACE_POP_DIRECT])
+    g.close()
 
 
 @pytest.mark.parametrize("w1_over_kappa", [0.5, 1.0, 4.0])
@@ -107,7 +123,7 @@ def test_edge_cases(ace, orc):
         with pytest.raises(ace.AceError):
             ace.Pop(*_args(2, (10, 12), 0, 0.1), omega1=bad)
     with pytest.raises(ace.AceError):
-        g.set_kernel(4)
+        g.set_kernel(5)
     bad = phi0.copy()
     bad[2, 3] = np.inf
     with pytest.raises(ace.AceError):

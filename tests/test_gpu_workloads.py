@@ -230,7 +230,10 @@ def oracle_64_full(orc, inputs):
 # (0 = persistent grid), and the autotuned choice itself
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("kernel,planes", [("march", None), ("tblock", 0), ("tblock", 40),
-                                           ("tblock", 16), ("auto", None)])
+                                           ("tblock", 16), ("auto", None),
+                                           ("tb3", (2, 32, 4, 0)), ("tb3", (3, 48, 3, 16)),
+                                           ("tb3", (3, 48, 4, 0)), ("tb3", (3, 32, 2, 32)),
+                                           ("tb3", (4, 32, 4, 0)), ("tb3", (4, 32, 2, 16))])
 def test_3d_periodic_64_full_length(ace, oracle_64_full, kernel, planes):
     """Same parameters as the 512^3 workload on a 64^3 grid (so the oracle can
     run it), node by node and monitor by monitor after all 5000 steps, on
@@ -244,11 +247,15 @@ def test_3d_periodic_64_full_length(ace, oracle_64_full, kernel, planes):
     elif kernel == "tblock":
         s.set_kernel(ace.ACE_KERNEL_TBLOCK)
         s.set_plane_chunk(planes)
+    elif kernel == "tb3":
+        s.set_kernel(ace.ACE_KERNEL_TBLOCK)
+        s.set_region3d(*planes[:3])
+        s.set_plane_chunk(planes[3])
     else:
         s.autotune(20)
         s.set_phi0(phi0)
     E, m = s.run_monitored(w.steps, w.every)
-    print(kernel, planes, s.get_kernel(), s.get_plane_chunk())
+    print(kernel, planes, s.get_kernel(), s.get_plane_chunk(), s.get_region3d())
     _check(s, E, m, want, Ew, mw)
     s.close()
 
