@@ -236,6 +236,33 @@ def batched_speedup(ace, torch):
             "resident_limit": tune["choice"]["resident_limit"], "depth": tune["choice"]["depth"]}
 
 
+def batch_launch(ace, torch, steps=500, depth=4, resident_limit=8000):
+    """The batched workload's persistent launch alone, at the autotuner's
+    usual choice (region depth 4, LDS limit 8000 nodes), issued directly
+    (no graph) so that counter tools see it: one untimed and one timed
+    launch of `steps` steps."""
+    from paper_2312_07010_amd import inputs
+    descs = inputs.batch_instances()
+    insts = [(x.d, [x.N] * x.d, [0.0] * x.d, [1.0] * x.d, x.eps, x.dt, x.bc) for x in descs]
+    b = ace.Batch(insts)
+    b.use_torch_stream()
+    b.set_graphs(False)
+    b.set_depth(depth)
+    b.set_resident_limit(resident_limit)
+    phi0 = [inputs.batch_phi0(i, shp) for i, shp in enumerate(b.shapes)]
+    b.set_all(phi0)
+    b.step(steps)
+    b.set_all(phi0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    updates = float(sum(b.totals)) * steps
+    b.close()
+    return {"seconds": t, "updates_per_s": updates / t, "depth": depth, "resident_limit": resident_limit}
+
+
 WORKLOAD_DESC = {
     "3d": "3D Allen-Cahn RLB-MIE-FD step, periodic, 512^3 nodes on (0,1)^3, eps 0.02, dt 5e-4, "
           "tanh sphere r 0.3 + U[-0.01,0.01] noise, energy + max-norm fused every 100 steps",
@@ -250,6 +277,8 @@ def kernel_name(ace, d, kernel, region=None):
     if kernel == ace.ACE_KERNEL_TBLOCK:
         if d == 3 and region is not None and region[1] > 0:
             return "k_tb3"
+        if d == 2 and region is not None and region[0] > 0:
+            return "k_tb2"
         return "k_tblock3d" if d == 3 else "k_tblock2d"
     return {ace.ACE_KERNEL_MARCH: "k_march3d", ace.ACE_KERNEL_DIRECT: "k_step_direct",
             ace.ACE_KERNEL_RESIDENT: "k_resident"}.get(kernel, str(kernel))
@@ -267,7 +296,7 @@ def launches_in(steps, every, per_launch):
 
 
 def timed_workload(ace, torch, w, kernel="auto", plane_chunk=-1, autotune=True, steps=None,
-                   warmup=100, every=100, keep=False, region3d=None):
+                   warmup=100, every=100, keep=False, region3d=None, region2d=None):
     """ace_run_monitored(steps, every) on the workload's field, resident in
     HBM, after `warmup` untimed steps; timed by the host clock and by HIP
     events on the solver's stream (torch's current stream)."""
@@ -283,7 +312,10 @@ def timed_workload(ace, torch, w, kernel="auto", plane_chunk=-1, autotune=True, 
     phi0_dev = torch.tensor(phi0, device="cuda")
     s.set_phi0(phi0_dev)
     tuning = None
-    if plane_chunk >= 0:
+    if region2d and w.d == 2:
+        s.set_kernel(ace.ACE_KERNEL_TBLOCK, region2d[2])
+        s.set_region2d(region2d[0], region2d[1])
+    elif plane_chunk >= 0:
         s.set_plane_chunk(plane_chunk)
         if region3d:
             s.set_kernel(ace.ACE_KERNEL_TBLOCK)
@@ -291,7 +323,7 @@ def timed_workload(ace, torch, w, kernel="auto", plane_chunk=-1, autotune=True, 
     elif kernel == "auto" and autotune:
         tuning = json.loads(s.autotune(20))
     k, per_launch = s.get_kernel()
-    region = s.get_region3d() if w.d == 3 else None
+    region = s.get_region3d() if w.d == 3 else (s.get_region2d() if w.d == 2 else None)
     s.set_phi0(phi0_dev)
     s.run_monitored(warmup, every)  # also loads every kernel variant used below
     torch.cuda.synchronize()
@@ -381,15 +413,19 @@ def main():
     ap.add_argument("--plane-chunk", type=int, default=-1, metavar="P",
                     help="fix the 3D blocked kernel's planes per workgroup, 0 = persistent grid "
                          "(skips the autotuner)")
+    ap.add_argument("--region2d", default="", metavar="R,T,K",
+                    help="2D workload without the autotuner: region rows R, rows per thread T (0,0: the "
+                         "LDS-plane kernel) and depth K")
     ap.add_argument("--region3d", default="", metavar="D,R,T",
                     help="with --plane-chunk: the 3D blocked kernel's depth D, region rows R and rows "
                          "per thread T (2,0,0: the two-step kernel)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="REPS",
                     help="only copy a 1 GiB device buffer REPS times (a plain copy kernel of "
                          "known size, for scaling HBM counters) and report its bandwidth")
-    ap.add_argument("--only", choices=["adjoint", "batched"], default=None,
+    ap.add_argument("--only", choices=["adjoint", "batched", "batch-launch"], default=None,
                     help="run only the adjoint-ratio or the batched measurement (for profiling) "
-                         "and print its result")
+                         "and print its result; batch-launch: only the batched workload's "
+                         "persistent launch, issued without graph replay (for counter collection)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -426,6 +462,9 @@ def main():
     if args.only == "batched":
         print(json.dumps(dict(only="batched", **batched_speedup(ace, torch))), flush=True)
         return
+    if args.only == "batch-launch":
+        print(json.dumps(dict(only="batch-launch", **batch_launch(ace, torch))), flush=True)
+        return
 
     if args.workload == "pop3d":
         w = inputs.W3D
@@ -449,8 +488,10 @@ def main():
     steps = args.steps or w.steps
     print(f"[bench] {w.name}: {steps} steps", file=sys.stderr, flush=True)
     region3d = tuple(int(v) for v in args.region3d.split(",")) if args.region3d else None
-    r = timed_workload(ace, torch, w, args.kernel, args.plane_chunk, not args.no_autotune, steps,
-                       args.warmup, args.every, keep=True, region3d=region3d)
+    region2d = tuple(int(v) for v in args.region2d.split(",")) if args.region2d else None
+    r = timed_workload(ace, torch, w, args.kernel, args.plane_chunk,
+                       not args.no_autotune and region2d is None, steps, args.warmup, args.every, keep=True,
+                       region3d=region3d, region2d=region2d)
     s = r["solver"]
     n = r["n"]
     value = n * steps / r["wall"]
@@ -482,6 +523,9 @@ def main():
         if r["region"] and r["region"][1] > 0:
             roof["region"] = {"depth": r["region"][0], "rows": r["region"][1], "cols": 64,
                               "rows_per_thread": r["region"][2]}
+    if w.d == 2 and r["region"] and r["region"][0] > 0:
+        roof["region"] = {"depth": r["per_launch"], "rows": r["region"][0], "cols": 64,
+                          "rows_per_thread": r["region"][1]}
     cc = committed_counters(r["kernel"], r["plane_chunk"], r["region"])
     if cc and cc[0] and cc[1] and "sq_per_launch" in cc[0]:
         # VALU issue time of one launch (committed SQ_INSTS_VALU x 64 lanes at

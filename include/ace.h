@@ -429,6 +429,11 @@ int ace_batch_set_all(ace_batch *b, const double *phi0_all, int where);
 int ace_batch_step(ace_batch *b, int64_t nsteps);
 /* Energy and max-norm of every instance (host arrays of count doubles). */
 int ace_batch_monitor(ace_batch *b, double *E, double *maxn);
+/* enable = 1 (default): each ace_batch_step replays a HIP graph holding the
+ * queue reset and the persistent launch (captured once per step count);
+ * 0: both launches are issued directly on the stream (e.g. for tools that
+ * do not follow graph launches).  Results are identical either way. */
+int ace_batch_set_graphs(ace_batch *b, int enable);
 int ace_batch_get_phi(ace_batch *b, int i, double *out, int where);
 int ace_batch_get_all(ace_batch *b, double *out_all, int where);
 /* Instances with at most `limit` stored nodes are stepped entirely in LDS

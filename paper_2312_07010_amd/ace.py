@@ -111,6 +111,7 @@ _SIGS = {
     "ace_batch_set_phi0": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int]),
     "ace_batch_set_all": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
     "ace_batch_step": (ctypes.c_int, [_vp, _i64]),
+    "ace_batch_set_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ace_batch_monitor": (ctypes.c_int, [_vp, _P(_dbl), _P(_dbl)]),
     "ace_batch_get_phi": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int]),
     "ace_batch_get_all": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
@@ -523,6 +524,9 @@ class Batch:
 
     def set_depth(self, depth):
         _check(lib().ace_batch_set_depth(self._h, int(depth)), "ace_batch_set_depth")
+
+    def set_graphs(self, enable):
+        _check(lib().ace_batch_set_graphs(self._h, int(bool(enable))), "ace_batch_set_graphs")
 
     def autotune(self, trial_steps=20):
         buf = ctypes.create_string_buffer(1 << 16)

@@ -334,6 +334,7 @@ struct ace_batch {
     double *arena_a = nullptr, *arena_b = nullptr;
     double *trip = nullptr;
     int grid = 0;
+    int use_graphs = 1;  // 0: the launch pair is issued directly on every step call
     std::map<int64_t, hipGraphExec_t> graphs;
     std::map<int64_t, hipGraph_t> graph_defs;
 };
@@ -541,9 +542,23 @@ int ace_batch_step(ace_batch *b, int64_t nsteps)
 {
     if (!b || nsteps < 0) return ACE_E_ARG;
     if (nsteps == 0) return ACE_OK;
+    if (!b->use_graphs) {
+        hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, b->stream, b->counter);
+        hipLaunchKernelGGL(k_batch, dim3(b->grid), dim3(kBT), 0, b->stream, b->inst, b->order_dev, b->count,
+                           b->counter, b->arena_a, b->arena_b, nsteps, b->depth);
+        BT_HIP(hipGetLastError());
+        return ACE_OK;
+    }
     hipGraphExec_t e = nullptr;
     BT_TRY(get_graph(b, nsteps, &e));
     BT_HIP(hipGraphLaunch(e, b->stream));
+    return ACE_OK;
+}
+
+int ace_batch_set_graphs(ace_batch *b, int enable)
+{
+    if (!b || (enable != 0 && enable != 1)) return ACE_E_ARG;
+    b->use_graphs = enable;
     return ACE_OK;
 }
 

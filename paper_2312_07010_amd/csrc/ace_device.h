@@ -34,21 +34,22 @@ __device__ __forceinline__ double approx_rcp(double d)
 // on the cubic; the host picks the start and nit by running this same
 // iteration in extended precision over a <= 1.  0 and 1 are exact fixed
 // points of both starts and of the step (f(0) = f(1) = 0), so 0 and +-1 are
-// returned exactly.  For a > 1 (only when the conditions fail) the lane
-// restarts from a and Newton continues until the correction stops mattering
-// (at most 200 steps); that test is one wavefront vote, so the common path
-// carries no per-lane branch.
+// returned exactly.  For a > 1 (only when the conditions fail) the start is
+// a and Newton continues until the correction stops mattering (at most 200
+// steps).
 template <bool S2>
 __device__ __forceinline__ double root_start_t(double a, const StepCoef &c)
 {
-    if (c.h > 0.5) return a;  // uniform
+    double x;
     if (S2) {
         const double a2 = a * a;
         const double f = fma(a2, a, -a);        // f(a)
         const double t = fma(-c.h3, a2, c.oph);  // 1 - h f'(a)
-        return fma(-(c.h * f), t, a);
+        x = fma(-(c.h * f), t, a);
+    } else {
+        x = fma(c.h * a, fma(-a, a, 1.0), a);
     }
-    return fma(c.h * a, fma(-a, a, 1.0), a);
+    return (a > 1.0 || c.h > 0.5) ? a : x;
 }
 
 __device__ __forceinline__ double root_start(double a, const StepCoef &c)
@@ -67,21 +68,6 @@ __host__ __device__ inline int root_variant(const StepCoef &c)
     return c.nit + 4 * c.start2;
 }
 
-// Newton on the cubic from a, to convergence (the rare case a > 1).
-__device__ __forceinline__ double root_far(double a, const StepCoef &c)
-{
-    double x = a;
-    for (int k = 0; k < 200; ++k) {
-        const double x2 = x * x;
-        const double p = fma(c.h, fma(x, x2, -x), x - a);
-        const double dp = fma(c.h3, x2, c.omh);
-        const double step = p / dp;
-        x -= step;
-        if (!(fabs(step) > 0x1p-54 * x)) break;
-    }
-    return x;
-}
-
 __device__ __forceinline__ double cubic_root(double xi, const StepCoef &c)
 {
     const double a = fabs(xi);
@@ -92,8 +78,15 @@ __device__ __forceinline__ double cubic_root(double xi, const StepCoef &c)
         const double dp = fma(c.h3, x2, c.omh);
         x = fma(-p, approx_rcp(dp), x);
     }
-    if (__any(a > 1.0)) {  // one vote per wavefront
-        if (a > 1.0) x = root_far(a, c);
+    if (a > 1.0) {
+        for (int k = 0; k < 200; ++k) {
+            const double x2 = x * x;
+            const double p = fma(c.h, fma(x, x2, -x), x - a);
+            const double dp = fma(c.h3, x2, c.omh);
+            const double step = p / dp;
+            x -= step;
+            if (!(fabs(step) > 0x1p-54 * x)) break;
+        }
     }
     return copysign(x, xi);
 }
@@ -116,8 +109,15 @@ __device__ __forceinline__ double cubic_root_n(double xi, const StepCoef &c)
         const double dp = fma(c.h3, x2, c.omh);
         x = fma(-p, approx_rcp(dp), x);
     }
-    if (__any(a > 1.0)) {  // one vote per wavefront
-        if (a > 1.0) x = root_far(a, c);
+    if (a > 1.0) {
+        for (int k = 0; k < 200; ++k) {
+            const double x2 = x * x;
+            const double p = fma(c.h, fma(x, x2, -x), x - a);
+            const double dp = fma(c.h3, x2, c.omh);
+            const double step = p / dp;
+            x -= step;
+            if (!(fabs(step) > 0x1p-54 * x)) break;
+        }
     }
     return copysign(x, xi);
 }

@@ -14,12 +14,21 @@
 //     through two LDS edge rows per wavefront, double-buffered by level
 //     parity (one workgroup barrier per level).
 // After level k only region rows k .. RH-1-k are still needed, so the rows
-// outside are skipped (wave-uniform tests).  Values outside the domain are
-// loaded BC-mapped (clamped / zero / wrapped); for Neumann and Dirichlet a
-// boundary node's outward neighbour is the node itself or 0 (the ring values
-// outside the domain are only right at level 0).  The arithmetic and the
-// neighbour order are those of the one-step kernels, so the result equals K
-// one-step launches bit for bit.  Monitors (MON) are those of the input
+// outside are skipped (wave-uniform tests).
+//
+// Nodes outside the domain are loaded as the images the boundary condition
+// makes of the field: periodic wraps; Neumann reflects about the wall half a
+// cell past the last node (the ghost next to node 0 holds node 0, the next
+// one node 1, ...); Dirichlet holds 0 at the wall node and the negated
+// reflection beyond it.  The step maps these images to the images of the
+// stepped field exactly: the update is odd in (node, neighbour sum) and the
+// pair sums are commutative, so a mirrored ghost computes its node's value
+// and a negated one its negative, bit for bit, and a Dirichlet wall node
+// stays 0.  So every node, in the domain or not, takes its plain neighbours,
+// and the boundary nodes get exactly the one-step kernels' values (Neumann:
+// the outward neighbour is the node itself; Dirichlet: 0) with no test per
+// node.  The arithmetic and the neighbour order are those of the one-step
+// kernels, so the result equals K one-step launches bit for bit.  Monitors (MON) are those of the input
 // field; LEVELS writes every level k to out + (k - 1) * level_stride (the
 // adjoint's segment recompute).
 #pragma once
@@ -31,14 +40,36 @@ namespace tb2 {
 
 constexpr int RX = 64;  // region width: one wavefront
 
+// Stored index of the node whose value (times *sign: +1, -1, or 0 for a
+// Dirichlet wall node) the boundary condition places at coordinate c of an
+// axis of n stored nodes (the ring may reach past the domain more than once
+// on tiny grids).
 template <int BC>
-__device__ __forceinline__ int64_t mapc(int64_t c, int64_t n)
+__device__ __forceinline__ int64_t image(int64_t c, int64_t n, int &sign)
 {
+    sign = 1;
     if (c >= 0 && c < n) return c;
-    if (BC == BC_HN) return c < 0 ? 0 : n - 1;
-    if (BC == BC_HD) return -1;
-    const int64_t r = c % n;  // the ring may wrap more than once on tiny grids
-    return r < 0 ? r + n : r;
+    if (BC == BC_P) {
+        const int64_t r = c % n;
+        return r < 0 ? r + n : r;
+    }
+    if (BC == BC_HN) {  // mirror about the walls at -1/2 and n - 1/2: period 2n
+        int64_t r = c % (2 * n);
+        if (r < 0) r += 2 * n;
+        return r < n ? r : 2 * n - 1 - r;
+    }
+    // Dirichlet: wall nodes at -1 and n (value 0), odd reflection about them:
+    // period 2 (n + 1) in u = c + 1
+    const int64_t P = 2 * (n + 1);
+    int64_t u = (c + 1) % P;
+    if (u < 0) u += P;
+    if (u == 0 || u == n + 1) {
+        sign = 0;
+        return 0;
+    }
+    if (u <= n) return u - 1;
+    sign = -1;
+    return P - u - 1;
 }
 
 // The next lower lane's value (CTRL 0x138, DPP wave_shr:1) or the next higher
@@ -76,25 +107,28 @@ __global__ __launch_bounds__(RX * TRW) void k_tb2(Shape s, StepCoef c, const dou
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t yr0 = (tile / tiles_x) * oy - K;  // global row of region row 0
     const int64_t xg = (tile % tiles_x) * ox - K + tx;
-    const int64_t mx = mapc<BC>(xg, s.M2);
+    int sx;
+    const int64_t mx = image<BC>(xg, s.M2, sx);
     const bool xin = xg >= 0 && xg < s.M2 && tx >= K && tx < RX - K;
-    const bool xb0 = (xg == 0), xb1 = (xg == s.M2 - 1);
+    const bool xb0 = (xg == 0);
 
-    // level 0, and per row: the output offset of a tile-interior node in the
-    // domain (-1 otherwise; also the monitor's node set) and the domain-edge
-    // flags (wave-uniform)
+    // level 0 (images outside the domain), and per row the output offset of
+    // a tile-interior node in the domain (-1 otherwise; also the monitor's
+    // node set)
     double v[RYT];
     int oof[RYT];
-    bool yb0[RYT], yb1[RYT];
+    bool yb0[RYT];
 #pragma unroll
     for (int r = 0; r < RYT; ++r) {
         const int ry = tr * RYT + r;
         const int64_t yg = yr0 + ry;
-        const int64_t my = mapc<BC>(yg, s.M1);
-        v[r] = (my < 0 || mx < 0) ? 0.0 : in[my * s.M2 + mx];
+        int sy;
+        const int64_t my = image<BC>(yg, s.M1, sy);
+        const int sg = sx * sy;
+        const double val = in[my * s.M2 + mx];
+        v[r] = (BC == BC_P || sg > 0) ? val : (sg < 0 ? -val : 0.0);
         oof[r] = (xin && ry >= K && ry < RH - K && yg >= 0 && yg < s.M1) ? (int)(yg * s.M2 + xg) : -1;
         yb0[r] = (yg == 0);
-        yb1[r] = (yg == s.M1 - 1);
     }
     eb(0, 0, tr)[tx] = v[0];
     eb(0, 1, tr)[tx] = v[RYT - 1];
@@ -114,14 +148,14 @@ __global__ __launch_bounds__(RX * TRW) void k_tb2(Shape s, StepCoef c, const dou
             const int ry = tr * RYT + r;
             if (ry < k || ry >= RH - k) continue;  // wave-uniform: a ring row of this level
             const double p = v[r];
-            double ym = (r > 0) ? v[r > 0 ? r - 1 : 0] : eT;
-            double yp = (r < RYT - 1) ? v[r < RYT - 1 ? r + 1 : 0] : eB;
-            double xm = lane_shift<0x138>(p);
-            double xp = lane_shift<0x130>(p);
+            const double ym = (r > 0) ? v[r > 0 ? r - 1 : 0] : eT;
+            const double yp = (r < RYT - 1) ? v[r < RYT - 1 ? r + 1 : 0] : eB;
+            const double xm = lane_shift<0x138>(p);
+            const double xp = lane_shift<0x130>(p);
             // (the monitor's nodes, the tile interior, are all level-1 rows)
             if (MON && k == 1 && oof[r] >= 0) {
                 // next-node differences with the BC value past the end (the
-                // loaded ring holds it), plus Dirichlet's first-node wall edge
+                // image there), plus Dirichlet's first-node wall edge
                 const double dy = yp - p, dx = xp - p;
                 double gr = fma(dy, dy, dx * dx);
                 if (BC == BC_HD) {
@@ -131,13 +165,6 @@ __global__ __launch_bounds__(RX * TRW) void k_tb2(Shape s, StepCoef c, const dou
                 m.bulk += bulk_term(p);
                 m.grad += gr;
                 m.mx = nan_max(m.mx, fabs(p));
-            }
-            if (BC != BC_P) {
-                const double wall = (BC == BC_HN) ? p : 0.0;
-                if (yb0[r]) ym = wall;
-                if (yb1[r]) yp = wall;
-                if (xb0) xm = wall;
-                if (xb1) xp = wall;
             }
             const double nsum = (ym + yp) + (xm + xp);
             const double val = update_n<2, RV>(p, nsum, c);

@@ -116,6 +116,28 @@ def test_region_depth_does_not_change_results(ace):
         assert np.array_equal(x, y)
 
 
+def test_direct_launches_equal_graph_replays(ace):
+    """ace_batch_set_graphs(0) issues the queue reset and the persistent
+    launch directly; every instance ends bit for bit where the graph replay
+    ends, over several calls in a row."""
+    insts = _mixed(3)
+    a = ace.Batch(insts)
+    b = ace.Batch(insts)
+    b.set_graphs(False)
+    rng = np.random.default_rng(12)
+    phi0 = [rng.uniform(-0.9, 0.9, shp) for shp in a.shapes]
+    a.set_all(phi0)
+    b.set_all(phi0)
+    for n in (9, 9, 4):
+        a.step(n)
+        b.step(n)
+        for x, y in zip(a.get_all(), b.get_all()):
+            assert np.array_equal(x, y)
+    assert ace.lib().ace_batch_set_graphs(b._h, 2) == ace.ACE_E_ARG
+    a.close()
+    b.close()
+
+
 def test_batch_repeated_steps_and_rejects_bad_instances(ace):
     insts = _mixed(2)[:10]
     b = ace.Batch(insts)
