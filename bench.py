@@ -233,14 +233,16 @@ def batched_speedup(ace, torch):
     return {"speedup": t_loop / t_batch, "batched_s": t_batch, "looped_s": t_loop,
             "batched_updates_per_s": updates / t_batch,
             "algorithmic_hbm_frac": BYTES_PER_UPDATE * updates / t_batch / HBM_PEAK,
-            "resident_limit": tune["choice"]["resident_limit"], "depth": tune["choice"]["depth"]}
+            "resident_limit": tune["choice"]["resident_limit"], "depth": tune["choice"]["depth"],
+            "region": tune["choice"]["region"]}
 
 
-def batch_launch(ace, torch, steps=500, depth=4, resident_limit=8000):
-    """The batched workload's persistent launch alone, at the autotuner's
-    usual choice (region depth 4, LDS limit 8000 nodes), issued directly
-    (no graph) so that counter tools see it: one untimed and one timed
-    launch of `steps` steps."""
+def batch_launch(ace, torch, steps=500, depth=4, resident_limit=8000, region=0):
+    """The batched workload's persistent launches alone, at a fixed choice
+    (region depth, LDS limit, region height: 0 for LDS-plane regions, 32 or
+    64 for register-resident ones in a kernel of their own), issued directly
+    (no graph) so that counter tools see them: one untimed and one timed
+    call of `steps` steps."""
     from paper_2312_07010_amd import inputs
     descs = inputs.batch_instances()
     insts = [(x.d, [x.N] * x.d, [0.0] * x.d, [1.0] * x.d, x.eps, x.dt, x.bc) for x in descs]
@@ -249,6 +251,7 @@ def batch_launch(ace, torch, steps=500, depth=4, resident_limit=8000):
     b.set_graphs(False)
     b.set_depth(depth)
     b.set_resident_limit(resident_limit)
+    b.set_region(region)
     phi0 = [inputs.batch_phi0(i, shp) for i, shp in enumerate(b.shapes)]
     b.set_all(phi0)
     b.step(steps)
@@ -260,7 +263,8 @@ def batch_launch(ace, torch, steps=500, depth=4, resident_limit=8000):
     t = time.perf_counter() - t0
     updates = float(sum(b.totals)) * steps
     b.close()
-    return {"seconds": t, "updates_per_s": updates / t, "depth": depth, "resident_limit": resident_limit}
+    return {"seconds": t, "updates_per_s": updates / t, "depth": depth, "resident_limit": resident_limit,
+            "region": region}
 
 
 WORKLOAD_DESC = {
@@ -416,6 +420,10 @@ def main():
     ap.add_argument("--region2d", default="", metavar="R,T,K",
                     help="2D workload without the autotuner: region rows R, rows per thread T (0,0: the "
                          "LDS-plane kernel) and depth K")
+    ap.add_argument("--batch-region", type=int, default=0, choices=[0, 32, 64], metavar="ROWS",
+                    help="batch-launch only: region height of the large 2D instances (0: LDS-plane regions)")
+    ap.add_argument("--batch-depth", type=int, default=4, metavar="K",
+                    help="batch-launch only: steps per region round")
     ap.add_argument("--region3d", default="", metavar="D,R,T",
                     help="with --plane-chunk: the 3D blocked kernel's depth D, region rows R and rows "
                          "per thread T (2,0,0: the two-step kernel)")
@@ -463,7 +471,8 @@ def main():
         print(json.dumps(dict(only="batched", **batched_speedup(ace, torch))), flush=True)
         return
     if args.only == "batch-launch":
-        print(json.dumps(dict(only="batch-launch", **batch_launch(ace, torch))), flush=True)
+        print(json.dumps(dict(only="batch-launch", **batch_launch(ace, torch, depth=args.batch_depth,
+                                                                      region=args.batch_region))), flush=True)
         return
 
     if args.workload == "pop3d":

@@ -445,11 +445,18 @@ int ace_batch_set_resident_limit(ace_batch *b, int64_t limit);
  * ring of `depth` nodes recomputed.  Results do not depend on the choice.
  * Error: ACE_E_ARG outside 1..8. */
 int ace_batch_set_depth(ace_batch *b, int depth);
+/* Region of the 2D instances too large for LDS: rows = 0 (default) the
+ * 32 x 64 regions kept in LDS level by level; 32 or 64 the register-resident
+ * regions of that many rows by 64 columns (each thread two or four rows of a
+ * column; nodes outside the instance are its boundary images), the region
+ * shape of ace_set_region2d.  Results do not depend on the choice.  Error:
+ * ACE_E_ARG for other values. */
+int ace_batch_set_region(ace_batch *b, int rows);
 /* Times one batch step of trial_steps steps on the current fields (which are
- * restored): first for depths 2..6 at the current resident limit, then for
- * several resident limits at the fastest depth.  Keeps the fastest pair and
- * writes a JSON record of the timings into json (capacity cap, may be
- * NULL). */
+ * restored): first for every region (0, 32, 64) and depth 2..6 at the
+ * current resident limit, then for several resident limits at the fastest
+ * pair.  Keeps the fastest and writes a JSON record of the timings into json
+ * (capacity cap, may be NULL). */
 int ace_batch_autotune(ace_batch *b, int64_t trial_steps, char *json, size_t cap);
 
 /* ---- autotuner ------------------------------------------------------------ */

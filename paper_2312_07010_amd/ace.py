@@ -112,6 +112,7 @@ _SIGS = {
     "ace_batch_set_all": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
     "ace_batch_step": (ctypes.c_int, [_vp, _i64]),
     "ace_batch_set_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "ace_batch_set_region": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ace_batch_monitor": (ctypes.c_int, [_vp, _P(_dbl), _P(_dbl)]),
     "ace_batch_get_phi": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int]),
     "ace_batch_get_all": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
@@ -524,6 +525,9 @@ class Batch:
 
     def set_depth(self, depth):
         _check(lib().ace_batch_set_depth(self._h, int(depth)), "ace_batch_set_depth")
+
+    def set_region(self, rows):
+        _check(lib().ace_batch_set_region(self._h, int(rows)), "ace_batch_set_region")
 
     def set_graphs(self, enable):
         _check(lib().ace_batch_set_graphs(self._h, int(bool(enable))), "ace_batch_set_graphs")

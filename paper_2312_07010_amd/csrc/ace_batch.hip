@@ -5,16 +5,20 @@
 // start first) and runs every step of that instance before taking another.
 // Instances whose field fits in LDS are stepped entirely in LDS (one global
 // read and one write per launch).  Larger 2D ones advance in rounds of up to
-// `depth` steps (1..8, autotuned; 4 by default) over 32 x 64 LDS regions
-// (temporal blocking, one global read and write per round); larger 1D ones
+// `depth` steps (1..8, autotuned; 4 by default) over 32 x 64 LDS regions or
+// register-resident regions of 32 or 64 rows (autotuned; temporal blocking,
+// one global read and write per round); larger 1D ones
 // ping-pong between their two arena slots with a workgroup barrier between
 // steps.  Every instance carries its own shape, boundary condition, kappa, h
 // and Newton count, and every update uses the same arithmetic as the
 // single-instance kernels, so each instance's result equals ace_step on that
 // instance bit for bit.
 //
-// The launch pair (counter reset by a one-thread kernel, then the persistent
-// kernel) is captured once per step count into a HIP graph and replayed.
+// With register-resident regions the large 2D instances are queued for a
+// kernel of their own (launched first, on the same stream), so that neither
+// kernel carries the other's register pressure.  The launches (counter reset
+// by a one-thread kernel, then the persistent kernels) are captured once per
+// step count into a HIP graph and replayed.
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -29,6 +33,7 @@
 #include "../../include/ace.h"
 #include "ace_device.h"
 #include "ace_runtime.h"
+#include "ace_tb2.h"
 #include "ace_tile2d.h"
 
 namespace ace {
@@ -237,28 +242,92 @@ __device__ void batch_tiles2d(const BatchInst &I, double *__restrict__ fa, doubl
     }
 }
 
-__global__ void k_batch_reset(int *counter)
+// The same rounds over register-resident regions (ace_tb2.h): each thread
+// holds RYT consecutive rows of a column of a (16 RYT) x 64 region, nodes
+// outside the instance are its boundary images, and the workgroup's LDS array
+// holds the regions' edge rows.  The next region's values are loaded while
+// the current one advances.
+template <int BC, int RYT>
+__device__ void batch_regions(const BatchInst &I, double *__restrict__ fa, double *__restrict__ fb,
+                              int64_t nsteps, double *lds, int tk)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0;
+    constexpr int TRW = kBT / 64;  // 16 wavefronts
+    using Rg = tb2::Region<BC, TRW, RYT>;
+    Shape s;
+    s.d = 2;
+    s.bc = BC;
+    s.M0 = 1;
+    s.M1 = I.M1;
+    s.M2 = I.M2;
+    MonAcc m;
+    mon_zero(m);
+    int64_t done = 0;
+    int par = 0;  // 0: the field is in fa
+    while (done < nsteps) {
+        const int K = (int)std::min<int64_t>(tk, nsteps - done);
+        const double *__restrict__ in = par ? fb : fa;
+        double *__restrict__ out = par ? fa : fb;
+        const int64_t oy = Rg::RH - 2 * K, ox = 64 - 2 * K;
+        const int64_t tiles_x = (s.M2 + ox - 1) / ox;
+        const int64_t ntiles = tiles_x * ((s.M1 + oy - 1) / oy);
+        double v[RYT], vn[RYT];
+        Rg(s, K, tiles_x, 0).load(s, in, v);
+#pragma unroll
+        for (int r = 0; r < RYT; ++r) vn[r] = 0.0;
+        for (int64_t t = 0; t < ntiles; ++t) {
+            const Rg g(s, K, tiles_x, t);
+            if (t + 1 < ntiles) Rg(s, K, tiles_x, t + 1).load(s, in, vn);
+            g.template advance<false, false, 0>(s, I.c, v, out, 0, lds, m);
+            __syncthreads();  // every wavefront is past the edge rows before the next region writes them
+#pragma unroll
+            for (int r = 0; r < RYT; ++r) v[r] = vn[r];
+        }
+        __threadfence_block();
+        __syncthreads();
+        done += K;
+        par ^= 1;
+    }
+    if (par) {  // result back into the first arena
+        for (int64_t j = threadIdx.x; j < s.M1 * s.M2; j += kBT) fa[j] = fb[j];
+        __threadfence_block();
+        __syncthreads();
+    }
 }
 
+__global__ void k_batch_reset(int *counter)
+{
+    if (threadIdx.x < 2 && blockIdx.x == 0) counter[threadIdx.x] = 0;
+}
+
+// The tasks order[first .. last) taken from the queue counter.  REGION = 0:
+// every kind of instance (large 2D ones over LDS-plane regions); 32 or 64:
+// large 2D instances only, over register-resident regions of that height.
+template <int REGION>
 __global__ __launch_bounds__(kBT) void k_batch(const BatchInst *__restrict__ inst,
-                                               const int *__restrict__ order, int ntasks,
+                                               const int *__restrict__ order, int first, int last,
                                                int *__restrict__ counter, double *__restrict__ arena_a,
                                                double *__restrict__ arena_b, int64_t nsteps, int tk)
 {
-    __shared__ double f[RESIDENT_MAX + 1];
+    __shared__ double f[REGION ? 2 * 2 * (kBT / 64) * 64 : RESIDENT_MAX + 1];
     __shared__ int task;
     for (;;) {
-        if (threadIdx.x == 0) task = atomicAdd(counter, 1);
+        if (threadIdx.x == 0) task = first + atomicAdd(counter, 1);
         __syncthreads();
-        const int t = task;
+        const int t = __builtin_amdgcn_readfirstlane(task);
         __syncthreads();  // all threads read the task before the next fetch
-        if (t >= ntasks) break;
+        if (t >= last) break;
         const BatchInst I = inst[order[t]];
         double *fa = arena_a + I.off;
         double *fb = arena_b + I.off;
-        if (I.resident) {
+        if (REGION == 64) {
+            if (I.bc == BC_HN) batch_regions<BC_HN, 4>(I, fa, fb, nsteps, f, tk);
+            else if (I.bc == BC_HD) batch_regions<BC_HD, 4>(I, fa, fb, nsteps, f, tk);
+            else batch_regions<BC_P, 4>(I, fa, fb, nsteps, f, tk);
+        } else if (REGION == 32) {
+            if (I.bc == BC_HN) batch_regions<BC_HN, 2>(I, fa, fb, nsteps, f, tk);
+            else if (I.bc == BC_HD) batch_regions<BC_HD, 2>(I, fa, fb, nsteps, f, tk);
+            else batch_regions<BC_P, 2>(I, fa, fb, nsteps, f, tk);
+        } else if (I.resident) {
             if (I.d == 1) {
                 if (I.bc == BC_HN) batch_resident<1, BC_HN>(I, fa, nsteps, f);
                 else if (I.bc == BC_HD) batch_resident<1, BC_HD>(I, fa, nsteps, f);
@@ -325,15 +394,18 @@ struct ace_batch {
     int64_t arena_total = 0;
     int64_t resident_limit = RESIDENT_MAX;  // tuned: largest field stepped in LDS
     int depth = 4;  // tuned: steps per round of the 2D instances stepped over LDS regions
+    int region = 0;  // tuned: 0 LDS-plane 32 x 64 regions; 32 or 64: register-resident regions of that height
     int device = 0;
     hipStream_t stream = nullptr;   // caller's stream (graph launches go here)
     hipStream_t capture = nullptr;  // private stream used only for graph capture
     BatchInst *inst = nullptr;
     int *order_dev = nullptr;
-    int *counter = nullptr;
+    int *counter = nullptr;  // [0] queue of the first kernel, [1] of the second
+    int n_large = 0;         // order[0 .. n_large): 2D instances too large for LDS (32-bit indexable)
     double *arena_a = nullptr, *arena_b = nullptr;
     double *trip = nullptr;
-    int grid = 0;
+    int grid = 0;     // workgroups of the queue kernel
+    int grid_rg = 0;  // workgroups of the register-region kernels
     int use_graphs = 1;  // 0: the launch pair is issued directly on every step call
     std::map<int64_t, hipGraphExec_t> graphs;
     std::map<int64_t, hipGraph_t> graph_defs;
@@ -367,16 +439,42 @@ int upload_tasks(ace_batch *b)
     // the tables below are read by any launch still running on the stream
     BT_HIP(hipStreamSynchronize(b->stream));
     for (auto &I : b->host_inst) I.resident = (I.total <= b->resident_limit) ? 1 : 0;
+    // the large 2D instances first (the register-region kernel's queue; the
+    // regions index a field with 32 bits), then the rest, each by cost
+    auto large = [&](int x) {
+        const BatchInst &I = b->host_inst[x];
+        return I.d == 2 && !I.resident && I.total <= INT32_MAX;
+    };
     b->order.resize(b->count);
     std::iota(b->order.begin(), b->order.end(), 0);
     std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
+        if (large(x) != large(y)) return large(x);
         return task_cost(b->host_inst[x]) > task_cost(b->host_inst[y]);
     });
+    b->n_large = (int)std::count_if(b->order.begin(), b->order.end(), large);
     BT_HIP(hipMemcpy(b->inst, b->host_inst.data(), sizeof(BatchInst) * b->count,
                      hipMemcpyHostToDevice));
     BT_HIP(hipMemcpy(b->order_dev, b->order.data(), sizeof(int) * b->count, hipMemcpyHostToDevice));
     drop_graphs(b);
     return ACE_OK;
+}
+
+// The batch kernels for the chosen region, on stream st (the counters must
+// be zero): the register-region kernel over the large 2D instances, then the
+// queue kernel over the rest; or the queue kernel over every instance.
+void launch_batch(const ace_batch *b, hipStream_t st, int64_t nsteps)
+{
+    auto go = [&](auto kern, int grid, int first, int last, int q) {
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kBT), 0, st, b->inst, b->order_dev, first, last, b->counter + q,
+                           b->arena_a, b->arena_b, nsteps, b->depth);
+    };
+    int first = 0;
+    if (b->region != 0 && b->n_large > 0) {
+        if (b->region == 64) go(k_batch<64>, b->grid_rg, 0, b->n_large, 0);
+        else go(k_batch<32>, b->grid_rg, 0, b->n_large, 0);
+        first = b->n_large;
+    }
+    if (first < b->count) go(k_batch<0>, b->grid, first, b->count, 1);
 }
 
 int get_graph(ace_batch *b, int64_t nsteps, hipGraphExec_t *out)
@@ -390,8 +488,7 @@ int get_graph(ace_batch *b, int64_t nsteps, hipGraphExec_t *out)
     hipGraphExec_t e = nullptr;
     BT_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, b->capture, b->counter);
-    hipLaunchKernelGGL(k_batch, dim3(b->grid), dim3(kBT), 0, b->capture, b->inst, b->order_dev,
-                       b->count, b->counter, b->arena_a, b->arena_b, nsteps, b->depth);
+    launch_batch(b, b->capture, nsteps);
     hipError_t le = hipGetLastError();
     hipError_t ce = hipStreamEndCapture(b->capture, &g);
     BT_HIP(le);
@@ -465,9 +562,14 @@ int ace_batch_create(int count, const ace_instance_desc *desc, ace_batch **out, 
     if ((rc = hip_status(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
                                                b->device))) < 0)
         return fail(rc);
-    if ((rc = hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, kBT, 0))) < 0)
+    if ((rc = hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<0>, kBT, 0))) < 0)
         return fail(rc);
     b->grid = std::max(1, cus * std::max(1, per_cu));
+    int per_cu_rg = 0, per_cu_rg32 = 0;
+    if ((rc = hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_rg, k_batch<64>, kBT, 0))) < 0 ||
+        (rc = hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_rg32, k_batch<32>, kBT, 0))) < 0)
+        return fail(rc);
+    b->grid_rg = std::max(1, cus * std::max(1, std::min(per_cu_rg, per_cu_rg32)));
     if ((rc = upload_tasks(b)) < 0) return fail(rc);
     *out = b;
     return warn;
@@ -544,14 +646,23 @@ int ace_batch_step(ace_batch *b, int64_t nsteps)
     if (nsteps == 0) return ACE_OK;
     if (!b->use_graphs) {
         hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, b->stream, b->counter);
-        hipLaunchKernelGGL(k_batch, dim3(b->grid), dim3(kBT), 0, b->stream, b->inst, b->order_dev, b->count,
-                           b->counter, b->arena_a, b->arena_b, nsteps, b->depth);
+        launch_batch(b, b->stream, nsteps);
         BT_HIP(hipGetLastError());
         return ACE_OK;
     }
     hipGraphExec_t e = nullptr;
     BT_TRY(get_graph(b, nsteps, &e));
     BT_HIP(hipGraphLaunch(e, b->stream));
+    return ACE_OK;
+}
+
+int ace_batch_set_region(ace_batch *b, int rows)
+{
+    if (!b || (rows != 0 && rows != 32 && rows != 64)) return ACE_E_ARG;
+    if (rows != b->region) {
+        b->region = rows;
+        drop_graphs(b);  // the captured launches carry the old region
+    }
     return ACE_OK;
 }
 
@@ -634,24 +745,28 @@ int ace_batch_autotune(ace_batch *b, int64_t trial_steps, char *json, size_t cap
     };
     int rc = hip_status(hipMemcpyAsync(save, b->arena_a, sizeof(double) * b->arena_total,
                                        hipMemcpyDeviceToDevice, b->stream));
-    // First the depth of the region rounds at the current resident limit,
-    // then the resident limit at the chosen depth.
+    // First the region shape and depth of the region rounds at the current
+    // resident limit, then the resident limit at the chosen pair.
     const int depths[] = {2, 3, 4, 5, 6};
+    const int regions[] = {0, 32, 64};
     const int64_t limits[] = {0, 1024, 2048, 4096, RESIDENT_MAX};
     double best_ms = 1e300;
     int64_t best_lim = b->resident_limit;
     int best_depth = b->depth;
+    int best_region = b->region;
     std::string rec = "{\"kind\": \"batch\", \"trial_steps\": " + std::to_string(trial_steps) +
-                      ", \"candidates\": [";
+                      ", \"workgroups\": " + std::to_string(b->grid) +
+                      ", \"workgroups_regions\": " + std::to_string(b->grid_rg) + ", \"candidates\": [";
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (rc >= 0) rc = hip_status(hipEventCreate(&e0));
     if (rc >= 0) rc = hip_status(hipEventCreate(&e1));
     bool first = true;
-    // times one batch step of trial_steps for (lim, depth); returns ms or a negative error
-    auto trial = [&](int64_t lim, int depth, double *ms_out) -> int {
+    // times one batch step of trial_steps for (lim, depth, region); returns ms or a negative error
+    auto trial = [&](int64_t lim, int depth, int region, double *ms_out) -> int {
         int r;
         if ((r = ace_batch_set_resident_limit(b, lim)) < 0) return r;
         if ((r = ace_batch_set_depth(b, depth)) < 0) return r;
+        if ((r = ace_batch_set_region(b, region)) < 0) return r;
         if ((r = restore()) < 0) return r;
         if ((r = ace_batch_step(b, trial_steps)) < 0) return r;  // builds the graph, warms up
         if ((r = restore()) < 0) return r;
@@ -663,28 +778,30 @@ int ace_batch_autotune(ace_batch *b, int64_t trial_steps, char *json, size_t cap
         if ((r = hip_status(hipEventElapsedTime(&ms, e0, e1))) < 0) return r;
         *ms_out = ms;
         char buf[160];
-        snprintf(buf, sizeof buf, "%s{\"resident_limit\": %lld, \"depth\": %d, \"ms\": %.4f}",
-                 first ? "" : ", ", (long long)lim, depth, ms);
+        snprintf(buf, sizeof buf, "%s{\"resident_limit\": %lld, \"depth\": %d, \"region\": %d, \"ms\": %.4f}",
+                 first ? "" : ", ", (long long)lim, depth, region, ms);
         rec += buf;
         first = false;
         return ACE_OK;
     };
     const int64_t lim0 = b->resident_limit;
-    for (int depth : depths) {
-        if (rc < 0) break;
-        double ms = 0.0;
-        if ((rc = trial(lim0, depth, &ms)) < 0) break;
-        if (ms < best_ms) {
-            best_ms = ms;
-            best_depth = depth;
-            best_lim = lim0;
+    for (int region : regions)
+        for (int depth : depths) {
+            if (rc < 0) break;
+            double ms = 0.0;
+            if ((rc = trial(lim0, depth, region, &ms)) < 0) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_depth = depth;
+                best_region = region;
+                best_lim = lim0;
+            }
         }
-    }
     for (int64_t lim : limits) {
         if (rc < 0) break;
         if (lim == lim0) continue;  // timed above at the chosen depth
         double ms = 0.0;
-        if ((rc = trial(lim, best_depth, &ms)) < 0) break;
+        if ((rc = trial(lim, best_depth, best_region, &ms)) < 0) break;
         if (ms < best_ms) {
             best_ms = ms;
             best_lim = lim;
@@ -694,15 +811,18 @@ int ace_batch_autotune(ace_batch *b, int64_t trial_steps, char *json, size_t cap
     if (e1) (void)hipEventDestroy(e1);
     if (rc >= 0) rc = ace_batch_set_resident_limit(b, best_lim);
     if (rc >= 0) rc = ace_batch_set_depth(b, best_depth);
+    if (rc >= 0) rc = ace_batch_set_region(b, best_region);
     if (rc >= 0) rc = restore();
     if (rc >= 0) rc = hip_status(hipStreamSynchronize(b->stream));
     (void)hipFree(save);
     if (rc < 0) return rc;
     rec += "], \"choice\": {\"resident_limit\": " + std::to_string(best_lim) +
-           ", \"depth\": " + std::to_string(best_depth) + "}}";
+           ", \"depth\": " + std::to_string(best_depth) + ", \"region\": " + std::to_string(best_region) + "}}";
     if (log_enabled())
-        fprintf(stderr, "[ace] batch autotune (%d instances): LDS limit %lld nodes, region depth %d, %.4f ms\n",
-                b->count, (long long)best_lim, best_depth, best_ms);
+        fprintf(stderr,
+                "[ace] batch autotune (%d instances): LDS limit %lld nodes, region depth %d, region rows %d, "
+                "%.4f ms\n",
+                b->count, (long long)best_lim, best_depth, best_region, best_ms);
     if (json && cap > 0) snprintf(json, cap, "%s", rec.c_str());
     return ACE_OK;
 }

@@ -90,96 +90,131 @@ struct Geom {
     static constexpr int KMAX = RH / 2 - 4;  // keeps an (RH - 2 KMAX = 8) x (64 - 2 KMAX) tile
 };
 
+// One region of the blocked 2D step, shared by the kernel below (one region
+// per workgroup) and the batched launch (each workgroup walks an instance's
+// regions in turn).  EB is the workgroup's edge-row buffer of
+// 2 * 2 * TRW * 64 doubles; `tile` numbers the (RH - 2K) x (64 - 2K) output
+// tiles row-major, tiles_x per row.
+template <int BC, int TRW, int RYT>
+struct Region {
+    using G = Geom<TRW, RYT>;
+    static constexpr int RH = G::RH;
+    int K, tx, tr;
+    int64_t yr0, xg, mx;
+    int sx;
+    bool xin, xb0;
+
+    __device__ __forceinline__ Region(const Shape &s, int K_, int64_t tiles_x, int64_t tile) : K(K_)
+    {
+        tx = threadIdx.x & (RX - 1);
+        tr = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront (uniform)
+        const int oy = RH - 2 * K, ox = RX - 2 * K;
+        yr0 = (tile / tiles_x) * oy - K;  // global row of region row 0
+        xg = (tile % tiles_x) * ox - K + tx;
+        mx = image<BC>(xg, s.M2, sx);
+        xin = xg >= 0 && xg < s.M2 && tx >= K && tx < RX - K;
+        xb0 = (xg == 0);
+    }
+
+    // level 0 of this thread's rows (images outside the domain)
+    __device__ __forceinline__ void load(const Shape &s, const double *__restrict__ in, double (&v)[RYT]) const
+    {
+#pragma unroll
+        for (int r = 0; r < RYT; ++r) {
+            int sy;
+            const int64_t my = image<BC>(yr0 + tr * RYT + r, s.M1, sy);
+            const int sg = sx * sy;
+            const double val = in[my * s.M2 + mx];
+            v[r] = (BC == BC_P || sg > 0) ? val : (sg < 0 ? -val : 0.0);
+        }
+    }
+
+    // Advances v (level 0, loaded) K levels; MON accumulates the monitor
+    // terms of level 0 over the tile interior into m; level K (LEVELS: every
+    // level k at out + (k - 1) * level_stride) goes to the tile interior.
+    // Ends with every wavefront past its last read of EB only if the caller
+    // adds a barrier before EB is written again.
+    template <bool MON, bool LEVELS, int RV>
+    __device__ __forceinline__ void advance(const Shape &s, const StepCoef &c, double (&v)[RYT],
+                                            double *__restrict__ out, int64_t level_stride, double *EB,
+                                            MonAcc &m) const
+    {
+        auto eb = [&](int par, int side, int w) -> double * { return EB + ((par * 2 + side) * TRW + w) * RX; };
+        // per row: the output offset of a tile-interior node in the domain (-1
+        // otherwise; also the monitor's node set)
+        int oof[RYT];
+        bool yb0[RYT];
+#pragma unroll
+        for (int r = 0; r < RYT; ++r) {
+            const int ry = tr * RYT + r;
+            const int64_t yg = yr0 + ry;
+            oof[r] = (xin && ry >= K && ry < RH - K && yg >= 0 && yg < s.M1) ? (int)(yg * s.M2 + xg) : -1;
+            yb0[r] = (yg == 0);
+        }
+        eb(0, 0, tr)[tx] = v[0];
+        eb(0, 1, tr)[tx] = v[RYT - 1];
+        __syncthreads();
+        for (int k = 1; k <= K; ++k) {
+            const int rd = (k - 1) & 1;
+            double eT = 0.0, eB = 0.0;
+            if (tr > 0) eT = eb(rd, 1, tr - 1)[tx];
+            if (tr < TRW - 1) eB = eb(rd, 0, tr + 1)[tx];
+            double nv[RYT];
+#pragma unroll
+            for (int r = 0; r < RYT; ++r) {
+                nv[r] = v[r];
+                const int ry = tr * RYT + r;
+                if (ry < k || ry >= RH - k) continue;  // wave-uniform: a ring row of this level
+                const double p = v[r];
+                const double ym = (r > 0) ? v[r > 0 ? r - 1 : 0] : eT;
+                const double yp = (r < RYT - 1) ? v[r < RYT - 1 ? r + 1 : 0] : eB;
+                const double xm = lane_shift<0x138>(p);
+                const double xp = lane_shift<0x130>(p);
+                // (the monitor's nodes, the tile interior, are all level-1 rows)
+                if (MON && k == 1 && oof[r] >= 0) {
+                    // next-node differences with the BC value past the end (the
+                    // image there), plus Dirichlet's first-node wall edge
+                    const double dy = yp - p, dx = xp - p;
+                    double gr = fma(dy, dy, dx * dx);
+                    if (BC == BC_HD) {
+                        if (yb0[r]) gr = fma(p, p, gr);
+                        if (xb0) gr = fma(p, p, gr);
+                    }
+                    m.bulk += bulk_term(p);
+                    m.grad += gr;
+                    m.mx = nan_max(m.mx, fabs(p));
+                }
+                const double nsum = (ym + yp) + (xm + xp);
+                const double val = update_n<2, RV>(p, nsum, c);
+                nv[r] = val;
+                if ((LEVELS || k == K) && oof[r] >= 0)
+                    out[(LEVELS ? (int64_t)(k - 1) * level_stride : 0) + oof[r]] = val;
+            }
+#pragma unroll
+            for (int r = 0; r < RYT; ++r) v[r] = nv[r];
+            if (k < K) {
+                eb(k & 1, 0, tr)[tx] = v[0];
+                eb(k & 1, 1, tr)[tx] = v[RYT - 1];
+                __syncthreads();
+            }
+        }
+    }
+};
+
 template <int BC, bool MON, bool LEVELS, int RV, int TRW, int RYT>
 __global__ __launch_bounds__(RX * TRW) void k_tb2(Shape s, StepCoef c, const double *__restrict__ in,
                                                   double *__restrict__ out, double *__restrict__ partials,
                                                   int K, int tiles_x, int64_t level_stride)
 {
-    using G = Geom<TRW, RYT>;
-    constexpr int NT = G::NT, RH = G::RH;
+    constexpr int NT = Geom<TRW, RYT>::NT;
     __shared__ double EB[2 * 2 * TRW * RX];  // [parity][top | bottom][wavefront][lane]
     __shared__ double red[3 * (NT / 64)];
-    const int tx = threadIdx.x & (RX - 1);
-    const int tr = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront (uniform)
-    auto eb = [&](int par, int side, int w) -> double * { return EB + ((par * 2 + side) * TRW + w) * RX; };
-
-    const int oy = RH - 2 * K, ox = RX - 2 * K;
-    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int64_t yr0 = (tile / tiles_x) * oy - K;  // global row of region row 0
-    const int64_t xg = (tile % tiles_x) * ox - K + tx;
-    int sx;
-    const int64_t mx = image<BC>(xg, s.M2, sx);
-    const bool xin = xg >= 0 && xg < s.M2 && tx >= K && tx < RX - K;
-    const bool xb0 = (xg == 0);
-
-    // level 0 (images outside the domain), and per row the output offset of
-    // a tile-interior node in the domain (-1 otherwise; also the monitor's
-    // node set)
+    const Region<BC, TRW, RYT> g(s, K, tiles_x, xcd_tile(blockIdx.x, gridDim.x));
     double v[RYT];
-    int oof[RYT];
-    bool yb0[RYT];
-#pragma unroll
-    for (int r = 0; r < RYT; ++r) {
-        const int ry = tr * RYT + r;
-        const int64_t yg = yr0 + ry;
-        int sy;
-        const int64_t my = image<BC>(yg, s.M1, sy);
-        const int sg = sx * sy;
-        const double val = in[my * s.M2 + mx];
-        v[r] = (BC == BC_P || sg > 0) ? val : (sg < 0 ? -val : 0.0);
-        oof[r] = (xin && ry >= K && ry < RH - K && yg >= 0 && yg < s.M1) ? (int)(yg * s.M2 + xg) : -1;
-        yb0[r] = (yg == 0);
-    }
-    eb(0, 0, tr)[tx] = v[0];
-    eb(0, 1, tr)[tx] = v[RYT - 1];
-    __syncthreads();
-
+    g.load(s, in, v);
     MonAcc m;
     mon_zero(m);
-    for (int k = 1; k <= K; ++k) {
-        const int rd = (k - 1) & 1;
-        double eT = 0.0, eB = 0.0;
-        if (tr > 0) eT = eb(rd, 1, tr - 1)[tx];
-        if (tr < TRW - 1) eB = eb(rd, 0, tr + 1)[tx];
-        double nv[RYT];
-#pragma unroll
-        for (int r = 0; r < RYT; ++r) {
-            nv[r] = v[r];
-            const int ry = tr * RYT + r;
-            if (ry < k || ry >= RH - k) continue;  // wave-uniform: a ring row of this level
-            const double p = v[r];
-            const double ym = (r > 0) ? v[r > 0 ? r - 1 : 0] : eT;
-            const double yp = (r < RYT - 1) ? v[r < RYT - 1 ? r + 1 : 0] : eB;
-            const double xm = lane_shift<0x138>(p);
-            const double xp = lane_shift<0x130>(p);
-            // (the monitor's nodes, the tile interior, are all level-1 rows)
-            if (MON && k == 1 && oof[r] >= 0) {
-                // next-node differences with the BC value past the end (the
-                // image there), plus Dirichlet's first-node wall edge
-                const double dy = yp - p, dx = xp - p;
-                double gr = fma(dy, dy, dx * dx);
-                if (BC == BC_HD) {
-                    if (yb0[r]) gr = fma(p, p, gr);
-                    if (xb0) gr = fma(p, p, gr);
-                }
-                m.bulk += bulk_term(p);
-                m.grad += gr;
-                m.mx = nan_max(m.mx, fabs(p));
-            }
-            const double nsum = (ym + yp) + (xm + xp);
-            const double val = update_n<2, RV>(p, nsum, c);
-            nv[r] = val;
-            if ((LEVELS || k == K) && oof[r] >= 0)
-                out[(LEVELS ? (int64_t)(k - 1) * level_stride : 0) + oof[r]] = val;
-        }
-#pragma unroll
-        for (int r = 0; r < RYT; ++r) v[r] = nv[r];
-        if (k < K) {
-            eb(k & 1, 0, tr)[tx] = v[0];
-            eb(k & 1, 1, tr)[tx] = v[RYT - 1];
-            __syncthreads();
-        }
-    }
+    g.template advance<MON, LEVELS, RV>(s, c, v, out, level_stride, EB, m);
     if (MON) block_reduce_store(m, red, partials + 3 * blockIdx.x);
 }
 

@@ -116,6 +116,49 @@ def test_region_depth_does_not_change_results(ace):
         assert np.array_equal(x, y)
 
 
+def test_register_regions_do_not_change_results(ace):
+    """The large 2D instances stepped over register-resident regions of 32 or
+    64 rows (in a kernel of their own, ahead of the queue kernel) at every
+    depth, with the resident limit at 8000 and at 0 (then even 3 x 3 grids,
+    whose ring wraps several times, take the region path, and the 1D ones
+    stream), by graph replay and by direct launch: every instance bit for bit
+    as over LDS-plane regions.  Other heights are rejected; the autotuner
+    times every region."""
+    insts = _mixed(2)
+    b = ace.Batch(insts)
+    rng = np.random.default_rng(11)
+    phi0 = [rng.uniform(-0.9, 0.9, shp) for shp in b.shapes]
+    b.set_all(phi0)
+    b.step(19)
+    ref = b.get_all()
+    for lim in (8000, 0):
+        b.set_resident_limit(lim)
+        for rows in (32, 64):
+            b.set_region(rows)
+            for depth in (1, 2, 4, 8):
+                b.set_depth(depth)
+                for graphs in (True, False):
+                    b.set_graphs(graphs)
+                    b.set_all(phi0)
+                    b.step(19)
+                    for i, (x, y) in enumerate(zip(b.get_all(), ref)):
+                        assert np.array_equal(x, y), (lim, rows, depth, graphs, insts[i])
+    for bad in (16, 48, -1, 128):
+        with pytest.raises(ace.AceError) as e:
+            b.set_region(bad)
+        assert e.value.code == ace.ACE_E_ARG
+    b.set_resident_limit(8000)
+    b.set_graphs(True)
+    rec = json.loads(b.autotune(5))
+    assert {c["region"] for c in rec["candidates"]} == {0, 32, 64}
+    assert rec["choice"]["region"] in (0, 32, 64)
+    b.set_all(phi0)
+    b.step(19)
+    for x, y in zip(b.get_all(), ref):
+        assert np.array_equal(x, y)
+    b.close()
+
+
 def test_direct_launches_equal_graph_replays(ace):
     """ace_batch_set_graphs(0) issues the queue reset and the persistent
     launch directly; every instance ends bit for bit where the graph replay
