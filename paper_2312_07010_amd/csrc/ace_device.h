@@ -151,10 +151,12 @@ __device__ __forceinline__ double update(double p, double nsum, const StepCoef &
     return cubic_root(explicit_part<D>(p, nsum, c), c);
 }
 
+// (RV > 0 implies the implicit scheme: root_variant gives 0 for the explicit
+// one, so only RV = 0 tests c.fex.)
 template <int D, int RV>
 __device__ __forceinline__ double update_n(double p, double nsum, const StepCoef &c)
 {
-    if (c.fex) return explicit_fex<D>(p, nsum, c);
+    if (RV <= 0 && c.fex) return explicit_fex<D>(p, nsum, c);
     return cubic_root_n<RV>(explicit_part<D>(p, nsum, c), c);
 }
 

@@ -154,17 +154,22 @@ struct Region {
         eb(0, 0, tr)[tx] = v[0];
         eb(0, 1, tr)[tx] = v[RYT - 1];
         __syncthreads();
-        for (int k = 1; k <= K; ++k) {
+        // Level k from level k - 1.  FULL: every row of this wavefront is
+        // computed at this level (no per-row test); STORE: the tile-interior
+        // results go to out.
+        auto level = [&](int k, auto FULLc, auto STOREc) __attribute__((always_inline)) {
+            constexpr bool FULL = decltype(FULLc)::value, STORE = decltype(STOREc)::value;
             const int rd = (k - 1) & 1;
             double eT = 0.0, eB = 0.0;
             if (tr > 0) eT = eb(rd, 1, tr - 1)[tx];
             if (tr < TRW - 1) eB = eb(rd, 0, tr + 1)[tx];
+            double *__restrict__ lout = out + (LEVELS ? (int64_t)(k - 1) * level_stride : 0);
             double nv[RYT];
 #pragma unroll
             for (int r = 0; r < RYT; ++r) {
                 nv[r] = v[r];
                 const int ry = tr * RYT + r;
-                if (ry < k || ry >= RH - k) continue;  // wave-uniform: a ring row of this level
+                if (!FULL && (ry < k || ry >= RH - k)) continue;  // wave-uniform: a ring row of this level
                 const double p = v[r];
                 const double ym = (r > 0) ? v[r > 0 ? r - 1 : 0] : eT;
                 const double yp = (r < RYT - 1) ? v[r < RYT - 1 ? r + 1 : 0] : eB;
@@ -187,17 +192,24 @@ struct Region {
                 const double nsum = (ym + yp) + (xm + xp);
                 const double val = update_n<2, RV>(p, nsum, c);
                 nv[r] = val;
-                if ((LEVELS || k == K) && oof[r] >= 0)
-                    out[(LEVELS ? (int64_t)(k - 1) * level_stride : 0) + oof[r]] = val;
+                if (STORE && oof[r] >= 0) lout[oof[r]] = val;
             }
 #pragma unroll
             for (int r = 0; r < RYT; ++r) v[r] = nv[r];
-            if (k < K) {
-                eb(k & 1, 0, tr)[tx] = v[0];
-                eb(k & 1, 1, tr)[tx] = v[RYT - 1];
-                __syncthreads();
-            }
+        };
+        using T = std::true_type;
+        using F = std::false_type;
+        const int row0 = tr * RYT;
+        for (int k = 1; k < K; ++k) {
+            const bool full = row0 >= k && row0 + RYT <= RH - k;
+            if (full) level(k, T(), std::integral_constant<bool, LEVELS>());
+            else level(k, F(), std::integral_constant<bool, LEVELS>());
+            eb(k & 1, 0, tr)[tx] = v[0];
+            eb(k & 1, 1, tr)[tx] = v[RYT - 1];
+            __syncthreads();
         }
+        if (row0 >= K && row0 + RYT <= RH - K) level(K, T(), T());
+        else level(K, F(), T());
     }
 };
 

@@ -193,6 +193,7 @@ __global__ __launch_bounds__(RX * TRW) __attribute__((amdgpu_waves_per_eu(OCC)))
             if (tr > 0) eT = eb(J - 1, rd, 1, tr - 1)[tx];
             if (tr < TRW - 1) eB = eb(J - 1, rd, 0, tr + 1)[tx];
             const bool mon_plane = MON && J == 1 && zo >= z0 && zo < z1;
+            double *__restrict__ oplane = out + zo * PS;  // (used at J == K only)
 #pragma unroll
             for (int r = 0; r < RYT; ++r) {
                 const int ry = tr * RYT + r;
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(RX * TRW) __attribute__((amdgpu_waves_per_eu(OCC)))
                 const double nsum = ((zm + zp) + (ym + yp)) + (xmv + xpv);
                 const double v = update_n<3, RV>(p, nsum, c);
                 if (J < K) dst[r] = v;
-                else if (oof[r] >= 0) out[zo * PS + oof[r]] = v;
+                else if (oof[r] >= 0) oplane[oof[r]] = v;
                 if (mon_plane && oof[r] >= 0) {
                     const double dz = zp - p, dy = yp - p, dx = xpv - p;
                     double g = fma(dz, dz, fma(dy, dy, dx * dx));
