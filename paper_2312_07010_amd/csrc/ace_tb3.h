@@ -51,6 +51,42 @@ __device__ __forceinline__ int64_t mapc(int64_t c, int64_t n)
     return r < 0 ? r + n : r;
 }
 
+// mapc of a plane index that advances one plane at a time, with its element
+// offset (mapped index times the plane size; -1 for the Dirichlet zero
+// plane), kept up to date by comparisons instead of a division and a product
+// per plane.
+template <int BC>
+struct PlaneCursor {
+    int64_t z, mz, off;
+    __device__ __forceinline__ void init(int64_t z0, int64_t n, int64_t PS)
+    {
+        z = z0;
+        mz = mapc<BC>(z0, n);
+        off = mz < 0 ? -1 : mz * PS;
+    }
+    __device__ __forceinline__ void next(int64_t n, int64_t PS)
+    {
+        ++z;
+        if (BC == BC_P) {  // (mz + 1) mod n
+            ++mz;
+            off += PS;
+            if (mz == n) {
+                mz = 0;
+                off = 0;
+            }
+        } else if (z <= 0) {  // below the domain (Neumann: node 0) or its first plane
+            mz = (BC == BC_HN || z == 0) ? 0 : -1;
+            off = (BC == BC_HN || z == 0) ? 0 : -1;
+        } else if (z < n) {  // the previous plane was z - 1, in the domain
+            mz = z;
+            off += PS;
+        } else if (BC == BC_HD) {  // past the domain: the zero wall
+            mz = -1;
+            off = -1;
+        }  // (Neumann past the domain: stays at node n - 1)
+    }
+};
+
 // The value of the next lower lane (CTRL = 0x138, DPP wave_shr:1) or the next
 // higher lane (CTRL = 0x130, wave_shl:1) of a 64-lane wavefront, moved
 // between registers by the DPP lane network in two 32-bit halves; lane 0
@@ -165,6 +201,12 @@ __global__ __launch_bounds__(RX * TRW) __attribute__((amdgpu_waves_per_eu(OCC)))
             for (int k = 0; k < 3; ++k)
 #pragma unroll
                 for (int r = 0; r < RYT; ++r) qj[j][k][r] = 0.0;
+        // the plane the next position loads, and the output offset of plane
+        // zc - K + 1 (level K's plane)
+        static_assert(K >= 2, "the cursor starts at the last plane loaded above");
+        PlaneCursor<BC> cur;
+        cur.init(zs + 2, s.M0, PS);
+        int64_t ooff = (zs - K + 1) * PS;
         // edges of level-0 plane zs, read at the first position
         eb(0, (int)((zs - 1) & 1), 0, tr)[tx] = q0[1][0];
         eb(0, (int)((zs - 1) & 1), 1, tr)[tx] = q0[1][RYT - 1];
@@ -193,7 +235,7 @@ __global__ __launch_bounds__(RX * TRW) __attribute__((amdgpu_waves_per_eu(OCC)))
             if (tr > 0) eT = eb(J - 1, rd, 1, tr - 1)[tx];
             if (tr < TRW - 1) eB = eb(J - 1, rd, 0, tr + 1)[tx];
             const bool mon_plane = MON && J == 1 && zo >= z0 && zo < z1;
-            double *__restrict__ oplane = out + zo * PS;  // (used at J == K only)
+            double *__restrict__ oplane = out + (J == K ? ooff : 0);  // plane zo (used at J == K only)
 #pragma unroll
             for (int r = 0; r < RYT; ++r) {
                 const int ry = tr * RYT + r;
@@ -247,7 +289,8 @@ __global__ __launch_bounds__(RX * TRW) __attribute__((amdgpu_waves_per_eu(OCC)))
             level(std::integral_constant<int, 1>(), q0[A0], q0[B0], q0[C0], qj[0][P2]);
             // next level-0 plane into the slot level 1 just freed
             {
-                const int64_t bn = base(zc + 3 <= zlast ? zc + 3 : zlast);
+                if (zc + 3 <= zlast) cur.next(s.M0, PS);  // plane min(zc + 3, zlast)
+                const int64_t bn = cur.off;
 #pragma unroll
                 for (int r = 0; r < RYT; ++r) q0[A0][r] = ld(bn, off[r]);
             }
@@ -272,6 +315,7 @@ __global__ __launch_bounds__(RX * TRW) __attribute__((amdgpu_waves_per_eu(OCC)))
             eb(0, (int)(zc & 1), 1, tr)[tx] = q0[C0][RYT - 1];
             __syncthreads();
             ++zc;
+            ooff += PS;
             return false;
         };
         for (;;) {
