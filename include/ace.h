@@ -163,7 +163,8 @@ int ace_set_kernel(ace_solver *s, int kernel, int depth);
  * (rows / rows_per_thread wavefronts per workgroup), with a ring of depth
  * nodes recomputed: (2, 32, 4), (3, 48, 3), (3, 48, 4), (3, 32, 2),
  * (4, 32, 4), (4, 32, 2).  ace_autotune chooses among all of them.  Runs
- * shorter than the depth take the two-step or one-step kernel.  Error:
+ * shorter than the depth, and planes (M1 * M2) of 2^28 nodes or more, take
+ * the two-step or one-step kernel.  Error:
  * ACE_E_ARG when d != 3 or the triple is not instantiated. */
 int ace_set_region3d(ace_solver *s, int depth, int rows, int rows_per_thread);
 int ace_get_region3d(const ace_solver *s, int *depth, int *rows, int *rows_per_thread);

@@ -51,6 +51,14 @@ __device__ __forceinline__ int64_t mapc(int64_t c, int64_t n)
     return r < 0 ? r + n : r;
 }
 
+// Raw buffer resources over one plane: the fourth descriptor word of
+// the gfx9 family, and a byte offset past any plane (2^31, with planes
+// below 2^31 bytes), at which a store falls outside the buffer and is
+// dropped by the hardware's range check instead of an execution mask.
+constexpr int kBufWord3 = 0x00020000;
+constexpr uint32_t kNoStore = 0x80000000u;
+using BufB64 = decltype(__builtin_amdgcn_raw_buffer_load_b64(__amdgpu_buffer_rsrc_t(), 0, 0, 0));
+
 // mapc of a plane index that advances one plane at a time, with its element
 // offset (mapped index times the plane size; -1 for the Dirichlet zero
 // plane), kept up to date by comparisons instead of a division and a product
@@ -154,19 +162,21 @@ __global__ __launch_bounds__(RX * TRW) __attribute__((amdgpu_waves_per_eu(OCC)))
         const int64_t mxc = mapc<BC>(xg, s.M2);
         const bool xb0 = (xg == 0), xb1 = (xg == s.M2 - 1);
 
-        // per row: mapped in-plane load offset (-1: Dirichlet zero), output
-        // offset (-1: ring or outside the domain), domain-edge flags (uniform)
-        int off[RYT], oof[RYT];
+        // per row: mapped in-plane load offset in bytes (-1: Dirichlet zero),
+        // output offset in bytes (kNoStore: ring or outside the domain),
+        // domain-edge flags (uniform)
+        int off[RYT];
+        uint32_t oof[RYT];
         bool yb0[RYT], yb1[RYT];
 #pragma unroll
         for (int r = 0; r < RYT; ++r) {
             const int ry = tr * RYT + r;
             const int64_t yg = yr0 + ry;
             const int64_t myc = mapc<BC>(yg, s.M1);
-            off[r] = (myc < 0 || mxc < 0) ? -1 : (int)(myc * s.M2 + mxc);
+            off[r] = (myc < 0 || mxc < 0) ? -1 : (int)(myc * s.M2 + mxc) * 8;
             const bool interior = ry >= K && ry < RH - K && tx >= K && tx < RX - K;
             const bool indomain = yg >= 0 && yg < s.M1 && xg >= 0 && xg < s.M2;
-            oof[r] = (interior && indomain) ? (int)(yg * s.M2 + xg) : -1;
+            oof[r] = (interior && indomain) ? (uint32_t)(yg * s.M2 + xg) * 8u : kNoStore;
             yb0[r] = (yg == 0);
             yb1[r] = (yg == s.M1 - 1);
         }
@@ -174,9 +184,15 @@ __global__ __launch_bounds__(RX * TRW) __attribute__((amdgpu_waves_per_eu(OCC)))
             const int64_t mz = mapc<BC>(z, s.M0);
             return mz < 0 ? -1 : mz * PS;
         };
+        // (a buffer over the input plane and a 32-bit byte offset per lane)
         auto ld = [&](int64_t b, int o) -> double {
-            if (BC != BC_HD) return in[b + o];
-            return (b < 0 || o < 0) ? 0.0 : in[b + o];
+            auto at = [&]() {
+                const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+                    const_cast<double *>(in) + (b < 0 ? 0 : b), (short)0, (int)(PS * 8), kBufWord3);
+                return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, o, 0, 0));
+            };
+            if (BC != BC_HD) return at();
+            return (b < 0 || o < 0) ? 0.0 : at();
         };
 
         // level-0 queue: slot k holds plane zs - 1 + k at the first position
@@ -235,7 +251,10 @@ __global__ __launch_bounds__(RX * TRW) __attribute__((amdgpu_waves_per_eu(OCC)))
             if (tr > 0) eT = eb(J - 1, rd, 1, tr - 1)[tx];
             if (tr < TRW - 1) eB = eb(J - 1, rd, 0, tr + 1)[tx];
             const bool mon_plane = MON && J == 1 && zo >= z0 && zo < z1;
-            double *__restrict__ oplane = out + (J == K ? ooff : 0);  // plane zo (used at J == K only)
+            // buffer over output plane zo (used at J == K only): rows at
+            // offset kNoStore fall outside it and are not written
+            const __amdgpu_buffer_rsrc_t orsrc =
+                __builtin_amdgcn_make_buffer_rsrc(out + (J == K ? ooff : 0), (short)0, (int)(PS * 8), kBufWord3);
 #pragma unroll
             for (int r = 0; r < RYT; ++r) {
                 const int ry = tr * RYT + r;
@@ -257,8 +276,8 @@ __global__ __launch_bounds__(RX * TRW) __attribute__((amdgpu_waves_per_eu(OCC)))
                 const double nsum = ((zm + zp) + (ym + yp)) + (xmv + xpv);
                 const double v = update_n<3, RV>(p, nsum, c);
                 if (J < K) dst[r] = v;
-                else if (oof[r] >= 0) oplane[oof[r]] = v;
-                if (mon_plane && oof[r] >= 0) {
+                else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(BufB64, v), orsrc, (int)oof[r], 0, 0);
+                if (mon_plane && oof[r] != kNoStore) {
                     const double dz = zp - p, dy = yp - p, dx = xpv - p;
                     double g = fma(dz, dz, fma(dy, dy, dx * dx));
                     if (BC == BC_HD) {

@@ -28,7 +28,8 @@ int64_t tb3_partials_v5(const Shape &, int);
 
 bool tb3_supported(const Shape &s)
 {
-    return s.d == 3 && s.M0 >= 1 && s.M1 >= 1 && s.M2 >= 1 && s.M1 * s.M2 < ((int64_t)1 << 31);
+    // (in-plane byte offsets and the output buffers are 32-bit: planes below 2^31 bytes)
+    return s.d == 3 && s.M0 >= 1 && s.M1 >= 1 && s.M2 >= 1 && s.M1 * s.M2 < ((int64_t)1 << 28);
 }
 
 int tb3_find(int depth, int rows, int rpt)
