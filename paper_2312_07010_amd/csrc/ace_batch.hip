@@ -246,8 +246,8 @@ __device__ void batch_tiles2d(const BatchInst &I, double *__restrict__ fa, doubl
 // holds RYT consecutive rows of a column of a (16 RYT) x 64 region, nodes
 // outside the instance are its boundary images, and the workgroup's LDS array
 // holds the regions' edge rows.  The next region's values are loaded while
-// the current one advances.
-template <int BC, int RYT>
+// the current one advances.  RV: the instance's root variant (ace_device.h).
+template <int BC, int RYT, int RV>
 __device__ void batch_regions(const BatchInst &I, double *__restrict__ fa, double *__restrict__ fb,
                               int64_t nsteps, double *lds, int tk)
 {
@@ -277,7 +277,7 @@ __device__ void batch_regions(const BatchInst &I, double *__restrict__ fa, doubl
         for (int64_t t = 0; t < ntiles; ++t) {
             const Rg g(s, K, tiles_x, t);
             if (t + 1 < ntiles) Rg(s, K, tiles_x, t + 1).load(s, in, vn);
-            g.template advance<false, false, 0>(s, I.c, v, out, 0, lds, m);
+            g.template advance<false, false, RV>(s, I.c, v, out, 0, lds, m);
             __syncthreads();  // every wavefront is past the edge rows before the next region writes them
 #pragma unroll
             for (int r = 0; r < RYT; ++r) v[r] = vn[r];
@@ -319,14 +319,18 @@ __global__ __launch_bounds__(kBT) void k_batch(const BatchInst *__restrict__ ins
         const BatchInst I = inst[order[t]];
         double *fa = arena_a + I.off;
         double *fb = arena_b + I.off;
-        if (REGION == 64) {
-            if (I.bc == BC_HN) batch_regions<BC_HN, 4>(I, fa, fb, nsteps, f, tk);
-            else if (I.bc == BC_HD) batch_regions<BC_HD, 4>(I, fa, fb, nsteps, f, tk);
-            else batch_regions<BC_P, 4>(I, fa, fb, nsteps, f, tk);
-        } else if (REGION == 32) {
-            if (I.bc == BC_HN) batch_regions<BC_HN, 2>(I, fa, fb, nsteps, f, tk);
-            else if (I.bc == BC_HD) batch_regions<BC_HD, 2>(I, fa, fb, nsteps, f, tk);
-            else batch_regions<BC_P, 2>(I, fa, fb, nsteps, f, tk);
+        if (REGION != 0) {
+            constexpr int RYT = REGION == 64 ? 4 : 2;
+            auto by_rv = [&](auto BCc) {
+                constexpr int B = decltype(BCc)::value;
+                // one Newton step from the plain start compiled in (the common
+                // case); other variants take the run-time root
+                if (root_variant(I.c) == 1) batch_regions<B, RYT, 1>(I, fa, fb, nsteps, f, tk);
+                else batch_regions<B, RYT, 0>(I, fa, fb, nsteps, f, tk);
+            };
+            if (I.bc == BC_HN) by_rv(std::integral_constant<int, BC_HN>());
+            else if (I.bc == BC_HD) by_rv(std::integral_constant<int, BC_HD>());
+            else by_rv(std::integral_constant<int, BC_P>());
         } else if (I.resident) {
             if (I.d == 1) {
                 if (I.bc == BC_HN) batch_resident<1, BC_HN>(I, fa, nsteps, f);
