@@ -267,20 +267,27 @@ __device__ void batch_regions(const BatchInst &I, double *__restrict__ fa, doubl
         const int K = (int)std::min<int64_t>(tk, nsteps - done);
         const double *__restrict__ in = par ? fb : fa;
         double *__restrict__ out = par ? fa : fb;
-        const int64_t oy = Rg::RH - 2 * K, ox = 64 - 2 * K;
-        const int64_t tiles_x = (s.M2 + ox - 1) / ox;
-        const int64_t ntiles = tiles_x * ((s.M1 + oy - 1) / oy);
+        const int oy = Rg::RH - 2 * K, ox = 64 - 2 * K;
+        const int tiles_x = ((int)s.M2 + ox - 1) / ox, tiles_y = ((int)s.M1 + oy - 1) / oy;
         double v[RYT], vn[RYT];
-        Rg(s, K, tiles_x, 0).load(s, in, v);
+        Rg(s, K, 0, 0).load(s, in, v);
 #pragma unroll
         for (int r = 0; r < RYT; ++r) vn[r] = 0.0;
-        for (int64_t t = 0; t < ntiles; ++t) {
-            const Rg g(s, K, tiles_x, t);
-            if (t + 1 < ntiles) Rg(s, K, tiles_x, t + 1).load(s, in, vn);
+        // regions row by row; the next one's values load while this one advances
+        for (int ty = 0, tx = 0; ty < tiles_y;) {
+            const Rg g(s, K, ty, tx);
+            int nty = ty, ntx = tx + 1;
+            if (ntx == tiles_x) {
+                ntx = 0;
+                ++nty;
+            }
+            if (nty < tiles_y) Rg(s, K, nty, ntx).load(s, in, vn);
             g.template advance<false, false, RV>(s, I.c, v, out, 0, lds, m);
             __syncthreads();  // every wavefront is past the edge rows before the next region writes them
 #pragma unroll
             for (int r = 0; r < RYT; ++r) v[r] = vn[r];
+            ty = nty;
+            tx = ntx;
         }
         __threadfence_block();
         __syncthreads();

@@ -43,25 +43,26 @@ constexpr int RX = 64;  // region width: one wavefront
 // Stored index of the node whose value (times *sign: +1, -1, or 0 for a
 // Dirichlet wall node) the boundary condition places at coordinate c of an
 // axis of n stored nodes (the ring may reach past the domain more than once
-// on tiny grids).
+// on tiny grids).  Fields here have fewer than 2^31 nodes, so coordinates
+// and offsets are 32-bit.
 template <int BC>
-__device__ __forceinline__ int64_t image(int64_t c, int64_t n, int &sign)
+__device__ __forceinline__ int image(int c, int n, int &sign)
 {
     sign = 1;
     if (c >= 0 && c < n) return c;
     if (BC == BC_P) {
-        const int64_t r = c % n;
+        const int r = c % n;
         return r < 0 ? r + n : r;
     }
     if (BC == BC_HN) {  // mirror about the walls at -1/2 and n - 1/2: period 2n
-        int64_t r = c % (2 * n);
+        int r = c % (2 * n);
         if (r < 0) r += 2 * n;
         return r < n ? r : 2 * n - 1 - r;
     }
     // Dirichlet: wall nodes at -1 and n (value 0), odd reflection about them:
     // period 2 (n + 1) in u = c + 1
-    const int64_t P = 2 * (n + 1);
-    int64_t u = (c + 1) % P;
+    const int P = 2 * (n + 1);
+    int u = (c + 1) % P;
     if (u < 0) u += P;
     if (u == 0 || u == n + 1) {
         sign = 0;
@@ -94,25 +95,28 @@ struct Geom {
 // per workgroup) and the batched launch (each workgroup walks an instance's
 // regions in turn).  EB is the workgroup's edge-row buffer of
 // 2 * 2 * TRW * 64 doubles; `tile` numbers the (RH - 2K) x (64 - 2K) output
-// tiles row-major, tiles_x per row.
+// tiles: tile row tile_y, column tile_x.  The field has fewer than 2^31
+// nodes (32-bit offsets).
 template <int BC, int TRW, int RYT>
 struct Region {
     using G = Geom<TRW, RYT>;
     static constexpr int RH = G::RH;
-    int K, tx, tr;
-    int64_t yr0, xg, mx;
+    int K, tx, tr, M1, M2;
+    int yr0, xg, mx;
     int sx;
     bool xin, xb0;
 
-    __device__ __forceinline__ Region(const Shape &s, int K_, int64_t tiles_x, int64_t tile) : K(K_)
+    __device__ __forceinline__ Region(const Shape &s, int K_, int tile_y, int tile_x) : K(K_)
     {
+        M1 = (int)s.M1;
+        M2 = (int)s.M2;
         tx = threadIdx.x & (RX - 1);
         tr = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront (uniform)
         const int oy = RH - 2 * K, ox = RX - 2 * K;
-        yr0 = (tile / tiles_x) * oy - K;  // global row of region row 0
-        xg = (tile % tiles_x) * ox - K + tx;
-        mx = image<BC>(xg, s.M2, sx);
-        xin = xg >= 0 && xg < s.M2 && tx >= K && tx < RX - K;
+        yr0 = tile_y * oy - K;  // global row of region row 0
+        xg = tile_x * ox - K + tx;
+        mx = image<BC>(xg, M2, sx);
+        xin = xg >= 0 && xg < M2 && tx >= K && tx < RX - K;
         xb0 = (xg == 0);
     }
 
@@ -122,9 +126,9 @@ struct Region {
 #pragma unroll
         for (int r = 0; r < RYT; ++r) {
             int sy;
-            const int64_t my = image<BC>(yr0 + tr * RYT + r, s.M1, sy);
+            const int my = image<BC>(yr0 + tr * RYT + r, M1, sy);
             const int sg = sx * sy;
-            const double val = in[my * s.M2 + mx];
+            const double val = in[my * M2 + mx];
             v[r] = (BC == BC_P || sg > 0) ? val : (sg < 0 ? -val : 0.0);
         }
     }
@@ -147,8 +151,8 @@ struct Region {
 #pragma unroll
         for (int r = 0; r < RYT; ++r) {
             const int ry = tr * RYT + r;
-            const int64_t yg = yr0 + ry;
-            oof[r] = (xin && ry >= K && ry < RH - K && yg >= 0 && yg < s.M1) ? (int)(yg * s.M2 + xg) : -1;
+            const int yg = yr0 + ry;
+            oof[r] = (xin && ry >= K && ry < RH - K && yg >= 0 && yg < M1) ? yg * M2 + xg : -1;
             yb0[r] = (yg == 0);
         }
         eb(0, 0, tr)[tx] = v[0];
@@ -221,7 +225,8 @@ __global__ __launch_bounds__(RX * TRW) void k_tb2(Shape s, StepCoef c, const dou
     constexpr int NT = Geom<TRW, RYT>::NT;
     __shared__ double EB[2 * 2 * TRW * RX];  // [parity][top | bottom][wavefront][lane]
     __shared__ double red[3 * (NT / 64)];
-    const Region<BC, TRW, RYT> g(s, K, tiles_x, xcd_tile(blockIdx.x, gridDim.x));
+    const int tile = (int)xcd_tile(blockIdx.x, gridDim.x);  // tiles numbered row-major
+    const Region<BC, TRW, RYT> g(s, K, tile / tiles_x, tile - (tile / tiles_x) * tiles_x);
     double v[RYT];
     g.load(s, in, v);
     MonAcc m;
