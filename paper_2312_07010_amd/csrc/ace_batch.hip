@@ -330,10 +330,16 @@ __global__ __launch_bounds__(kBT) void k_batch(const BatchInst *__restrict__ ins
             constexpr int RYT = REGION == 64 ? 4 : 2;
             auto by_rv = [&](auto BCc) {
                 constexpr int B = decltype(BCc)::value;
-                // one Newton step from the plain start compiled in (the common
-                // case); other variants take the run-time root
-                if (root_variant(I.c) == 1) batch_regions<B, RYT, 1>(I, fa, fb, nsteps, f, tk);
-                else batch_regions<B, RYT, 0>(I, fa, fb, nsteps, f, tk);
+                // every root variant with an instantiation compiled in (the
+                // explicit scheme and more than 3 Newton steps: the run-time root)
+                switch (root_variant(I.c)) {
+                case 1: batch_regions<B, RYT, 1>(I, fa, fb, nsteps, f, tk); break;
+                case 2: batch_regions<B, RYT, 2>(I, fa, fb, nsteps, f, tk); break;
+                case 3: batch_regions<B, RYT, 3>(I, fa, fb, nsteps, f, tk); break;
+                case 5: batch_regions<B, RYT, 5>(I, fa, fb, nsteps, f, tk); break;
+                case 6: batch_regions<B, RYT, 6>(I, fa, fb, nsteps, f, tk); break;
+                default: batch_regions<B, RYT, 0>(I, fa, fb, nsteps, f, tk); break;
+                }
             };
             if (I.bc == BC_HN) by_rv(std::integral_constant<int, BC_HN>());
             else if (I.bc == BC_HD) by_rv(std::integral_constant<int, BC_HD>());
