@@ -225,13 +225,16 @@ def oracle_64_full(orc, inputs):
     return w, phi0, want, Ew, mw
 
 
-# (kernel, plane chunk): the one-step marching kernel, the benchmark's
-# two-step blocked kernel at the launch shapes its autotuner picks between
-# (0 = persistent grid), and the autotuned choice itself
+# (kernel, plane chunk): the one-step marching kernel, the two-step LDS-plane
+# kernel at the launch shapes its autotuner picks between (0 = persistent
+# grid), every register-region variant (the 512^3 workload's autotuned
+# choices among them: depth 2 at 32 planes, depth 3 at 64), and the
+# autotuned choice itself
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("kernel,planes", [("march", None), ("tblock", 0), ("tblock", 40),
                                            ("tblock", 16), ("auto", None),
-                                           ("tb3", (2, 32, 4, 0)), ("tb3", (3, 48, 3, 16)),
+                                           ("tb3", (2, 32, 4, 0)), ("tb3", (2, 32, 4, 32)),
+                                           ("tb3", (3, 48, 3, 16)), ("tb3", (3, 48, 3, 64)),
                                            ("tb3", (3, 48, 4, 0)), ("tb3", (3, 32, 2, 32)),
                                            ("tb3", (4, 32, 4, 0)), ("tb3", (4, 32, 2, 16))])
 def test_3d_periodic_64_full_length(ace, oracle_64_full, kernel, planes):
