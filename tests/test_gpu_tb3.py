@@ -92,6 +92,32 @@ def test_variants_leave_nan_margins_untouched(ace, orc, bc):
     s.close()
 
 
+@pytest.mark.parametrize("bc", [0, 1, 2])
+def test_variants_with_values_beyond_one(ace, orc, bc):
+    """Initial values up to 1.6 in magnitude put |xi| > 1 at many nodes, where
+    the root continues past its fixed Newton steps: every variant still
+    equals the one-step kernel bit for bit, and the oracle."""
+    s, p = _box(ace, orc, (19, 37, 70), bc)
+    phi0 = np.random.default_rng(70 + bc).uniform(-1.6, 1.6, p.shape)
+    want, Ew, _ = p.run(phi0, 9, 3)
+    s.set_kernel(ace.ACE_KERNEL_DIRECT)
+    s.set_phi0(phi0)
+    Ed, md = s.run_monitored(9, 3)
+    ref = s.get_phi()
+    np.testing.assert_allclose(ref, want, rtol=0, atol=1e-12)
+    s.set_kernel(ace.ACE_KERNEL_TBLOCK)
+    for v in VARIANTS:
+        for planes in (0, 16):
+            s.set_region3d(*v)
+            s.set_plane_chunk(planes)
+            s.set_phi0(phi0)
+            E, m = s.run_monitored(9, 3)
+            assert np.array_equal(s.get_phi(), ref), (v, planes)
+            assert np.array_equal(m, md), (v, planes)
+            np.testing.assert_allclose(E, Ed, rtol=1e-13)
+    s.close()
+
+
 def test_region_arguments(ace, orc):
     s, _ = _box(ace, orc, (20, 20, 20), 2)
     for bad in [(3, 32, 4), (5, 32, 4), (2, 32, 0), (4, 64, 4)]:
