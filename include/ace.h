@@ -409,8 +409,10 @@ typedef struct {
 /* Creates a batch of count instances (each validated as ace_create does;
  * status[i] receives each instance's status when status is not NULL).
  * Allocates one device arena for all fields.  Instances of one batch run in
- * one persistent launch: each workgroup takes whole instances, one at a
- * time, from a queue ordered by decreasing cost, and runs all their steps. */
+ * persistent launches: each workgroup takes whole instances, one at a time,
+ * from a queue ordered by decreasing cost, and runs all their steps (with
+ * register-resident regions, the large 2D instances first in a kernel of
+ * their own, then the rest; see ace_batch_set_region). */
 int ace_batch_create(int count, const ace_instance_desc *desc,
                      ace_batch **out, int *status);
 int ace_batch_destroy(ace_batch *b);
@@ -426,14 +428,14 @@ int ace_batch_set_phi0(ace_batch *b, int i, const double *phi0, int where);
 /* Sets every instance's phi^0 from one host array holding all instances
  * back to back in instance order (sum of totals doubles). */
 int ace_batch_set_all(ace_batch *b, const double *phi0_all, int where);
-/* Advances every instance by nsteps in one persistent launch. */
+/* Advances every instance by nsteps (asynchronous on the batch's stream). */
 int ace_batch_step(ace_batch *b, int64_t nsteps);
 /* Energy and max-norm of every instance (host arrays of count doubles). */
 int ace_batch_monitor(ace_batch *b, double *E, double *maxn);
 /* enable = 1 (default): each ace_batch_step replays a HIP graph holding the
- * queue reset and the persistent launch (captured once per step count);
- * 0: both launches are issued directly on the stream (e.g. for tools that
- * do not follow graph launches).  Results are identical either way. */
+ * queue reset and the persistent launches (captured once per step count);
+ * 0: they are issued directly on the stream (e.g. for tools that do not
+ * follow graph launches).  Results are identical either way. */
 int ace_batch_set_graphs(ace_batch *b, int enable);
 int ace_batch_get_phi(ace_batch *b, int i, double *out, int where);
 int ace_batch_get_all(ace_batch *b, double *out_all, int where);
@@ -442,16 +444,17 @@ int ace_batch_get_all(ace_batch *b, double *out_all, int where);
  * through their two arena slots.  Results do not depend on the choice. */
 int ace_batch_set_resident_limit(ace_batch *b, int64_t limit);
 /* Steps per round (temporal-blocking depth, 1..8, default 4) of the 2D
- * instances too large for LDS, which advance over 32 x 64 LDS regions with a
- * ring of `depth` nodes recomputed.  Results do not depend on the choice.
- * Error: ACE_E_ARG outside 1..8. */
+ * instances too large for LDS, which advance over the regions of
+ * ace_batch_set_region with a ring of `depth` nodes recomputed.  Results do
+ * not depend on the choice.  Error: ACE_E_ARG outside 1..8. */
 int ace_batch_set_depth(ace_batch *b, int depth);
 /* Region of the 2D instances too large for LDS: rows = 0 (default) the
  * 32 x 64 regions kept in LDS level by level; 32 or 64 the register-resident
  * regions of that many rows by 64 columns (each thread two or four rows of a
  * column; nodes outside the instance are its boundary images), the region
- * shape of ace_set_region2d.  Results do not depend on the choice.  Error:
- * ACE_E_ARG for other values. */
+ * shape of ace_set_region2d, stepped by a kernel of their own launched before
+ * the one for the other instances.  Results do not depend on the choice.
+ * Error: ACE_E_ARG for other values. */
 int ace_batch_set_region(ace_batch *b, int rows);
 /* Times one batch step of trial_steps steps on the current fields (which are
  * restored): first for every region (0, 32, 64) and depth 2..6 at the
