@@ -71,16 +71,40 @@ def test_1d_periodic_256_full(ace, orc, inputs):
         _check(s, E, m, want, Ew, mw)
 
 
-@pytest.mark.timeout(900)
-def test_2d_neumann_1024_full(ace, orc, inputs):
+@pytest.fixture(scope="module")
+def oracle_2d_full(orc, inputs):
+    """The oracle's full 2D workload run (1024^2 x 10000), computed once."""
     w = inputs.W2D
-    s, p, E, m, want, Ew, mw = _run_both(ace, orc, w)
+    p = orc.Problem(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
+    phi0 = inputs.initial_field(w, p.shape, [p.coords(a) for a in range(w.d)])
+    want, Ew, mw = p.run(phi0, w.steps, w.every)
+    return w, phi0, want, Ew, mw
+
+
+# the default kernel choice, the register-region kernel on 64 x 64 regions at
+# depth 8 (the 2D workload's autotuned launch), and the autotuned choice
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("config", ["default", "tb2_64x4_k8", "auto"])
+def test_2d_neumann_1024_full(ace, oracle_2d_full, config):
+    w, phi0, want, Ew, mw = oracle_2d_full
+    s = ace.Solver(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
     assert s.shape == (1024, 1024)
+    assert np.array_equal(phi0, w_field(w, s))  # both sides' node coordinates agree
+    if config == "tb2_64x4_k8":
+        s.set_kernel(ace.ACE_KERNEL_TBLOCK, 8)
+        s.set_region2d(64, 4)
+    elif config == "auto":
+        s.set_phi0(phi0)
+        print(s.autotune(20))
+    s.set_phi0(phi0)
+    E, m = s.run_monitored(w.steps, w.every)
+    print(config, s.get_kernel(), s.get_region2d())
     _check(s, E, m, want, Ew, mw)
     # Theorems 2-3 hold along the run (conditions satisfied)
     assert s.params["conditions_ok"] == 1
     assert m.max() <= 1.0
     assert np.all(np.diff(E) <= 1e-14 * np.abs(E[:-1]))
+    s.close()
 
 
 def _subbox_oracle(orc, w, phi0, centre, T, kappa, h, scheme=0):
