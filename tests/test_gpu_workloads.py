@@ -144,14 +144,24 @@ def test_3d_periodic_512_sampled(ace, orc, inputs):
 
 
 @pytest.mark.timeout(600)
-def test_3d_periodic_512_fex_sampled(ace, orc, inputs):
-    """The fully explicit comparison scheme on the benchmark field and kernel
-    (its extra line in the benchmark): sampled nodes after 1 and 20 steps."""
+@pytest.mark.parametrize("config", ["default", "auto", (3, 48, 3, 64), (2, 32, 4, 32)])
+def test_3d_periodic_512_fex_sampled(ace, orc, inputs, config):
+    """The fully explicit comparison scheme on the benchmark field (its extra
+    line in the benchmark, which runs on the autotuned launch), on the
+    default kernel, the autotuned choice and both register-region shapes the
+    autotuner picks between: sampled nodes after 1 and 20 steps."""
     w = inputs.W3D
     s = ace.Solver(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
     p = orc.Problem(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
-    s.set_scheme(ace.ACE_SCHEME_FEX)
     phi0 = w_field(w, s)
+    if config == "auto":
+        s.set_phi0(phi0)
+        s.autotune(20)
+    elif config != "default":
+        s.set_kernel(ace.ACE_KERNEL_TBLOCK)
+        s.set_region3d(*config[:3])
+        s.set_plane_chunk(config[3])
+    s.set_scheme(ace.ACE_SCHEME_FEX)
     rng = np.random.default_rng(6)
     samples = [tuple(int(v) for v in rng.integers(0, 512, 3)) for _ in range(16)]
     samples += [(0, 0, 0), (511, 511, 511), (256, 256, 256 + 154), (256 - 154, 256, 256)]
