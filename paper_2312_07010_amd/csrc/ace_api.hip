@@ -183,6 +183,7 @@ StepCoef coef_of(const Problem &p)
     c.omh = 1.0 - p.h;
     c.oph = 1.0 + p.h;
     c.h3 = 3.0 * p.h;
+    c.hs = p.h > 0.5 ? 0.0 : p.h;
     c.nit = p.nit;
     c.start2 = p.start2;
     c.fex = (p.scheme == ACE_SCHEME_FEX) ? 1 : 0;

@@ -261,6 +261,7 @@ __device__ void batch_regions(const BatchInst &I, double *__restrict__ fa, doubl
     s.M2 = I.M2;
     MonAcc m;
     mon_zero(m);
+    const StepCoef c = coef_vgpr(I.c);
     int64_t done = 0;
     int par = 0;  // 0: the field is in fa
     while (done < nsteps) {
@@ -282,7 +283,7 @@ __device__ void batch_regions(const BatchInst &I, double *__restrict__ fa, doubl
                 ++nty;
             }
             if (nty < tiles_y) Rg(s, K, nty, ntx).load(s, in, vn);
-            g.template advance<false, false, RV>(s, I.c, v, out, 0, lds, m);
+            g.template advance<false, false, RV>(s, c, v, out, 0, lds, m);
             __syncthreads();  // every wavefront is past the edge rows before the next region writes them
 #pragma unroll
             for (int r = 0; r < RYT; ++r) v[r] = vn[r];

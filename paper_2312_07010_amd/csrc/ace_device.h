@@ -29,27 +29,26 @@ __device__ __forceinline__ double approx_rcp(double d)
 // restored.  For a <= 1 (always the case under Theorem 2's conditions) it
 // starts from the expansion of the root in h, to first order,
 // theta_0 = a - h f(a) = a + h a (1 - a^2), or (c.start2) to second order,
-// theta_0 = a - h f(a) (1 - h f'(a)) with f' = 3 a^2 - 1 (from theta_0 = a
-// when h > 1/2, where the expansion is poor), and takes `nit` Newton steps
-// on the cubic; the host picks the start and nit by running this same
-// iteration in extended precision over a <= 1.  0 and 1 are exact fixed
-// points of both starts and of the step (f(0) = f(1) = 0), so 0 and +-1 are
-// returned exactly.  For a > 1 (only when the conditions fail) the start is
-// a and Newton continues until the correction stops mattering (at most 200
-// steps).
+// theta_0 = a - h f(a) (1 - h f'(a)) with f' = 3 a^2 - 1, and takes `nit`
+// Newton steps on the cubic; the host picks the start and nit by running
+// this same iteration in extended precision over a <= 1.  When h > 1/2 the
+// expansion is poor and the start is a itself: the expansion's h is then
+// c.hs = 0, which gives a exactly (a + 0 * (finite) = a), so no lane selects.
+// 0 and 1 are exact fixed points of both starts and of the step
+// (f(0) = f(1) = 0), so 0 and +-1 are returned exactly.  For a > 1 (only
+// when the conditions fail) the iteration starts from a instead, takes the
+// same `nit` steps and continues until the correction stops mattering (at
+// most 200 more steps).
 template <bool S2>
 __device__ __forceinline__ double root_start_t(double a, const StepCoef &c)
 {
-    double x;
     if (S2) {
         const double a2 = a * a;
         const double f = fma(a2, a, -a);        // f(a)
         const double t = fma(-c.h3, a2, c.oph);  // 1 - h f'(a)
-        x = fma(-(c.h * f), t, a);
-    } else {
-        x = fma(c.h * a, fma(-a, a, 1.0), a);
+        return fma(-(c.hs * f), t, a);
     }
-    return (a > 1.0 || c.h > 0.5) ? a : x;
+    return fma(c.hs * a, fma(-a, a, 1.0), a);
 }
 
 __device__ __forceinline__ double root_start(double a, const StepCoef &c)
@@ -68,26 +67,54 @@ __host__ __device__ inline int root_variant(const StepCoef &c)
     return c.nit + 4 * c.start2;
 }
 
-__device__ __forceinline__ double cubic_root(double xi, const StepCoef &c)
+// A copy of c with omh and oph held in vector registers.  A VOP3
+// instruction reads at most one scalar register, so fma(h3, x^2, omh) of the
+// Newton step and fma(-h3, a^2, oph) of the second-order start, with both
+// coefficients in scalar registers, cost a move at every node; a kernel that
+// passes this copy to the root pays those moves once.  (The empty asm only
+// makes the values look per-lane to the compiler; it emits no instruction.)
+__device__ __forceinline__ StepCoef coef_vgpr(const StepCoef &c)
 {
-    const double a = fabs(xi);
-    double x = root_start(a, c);
-    for (int k = 0; k < c.nit; ++k) {
+    StepCoef v = c;
+    asm volatile("" : "+v"(v.omh), "+v"(v.oph));
+    return v;
+}
+
+// One Newton step on the cubic from x, with the reciprocal of the
+// derivative from its hardware estimate and one correction.
+__device__ __forceinline__ double newton_step(double x, double a, const StepCoef &c)
+{
+    const double x2 = x * x;
+    const double p = fma(c.h, fma(x, x2, -x), x - a);
+    const double dp = fma(c.h3, x2, c.omh);
+    return fma(-p, approx_rcp(dp), x);
+}
+
+// Newton steps with a true division from x until the correction stops
+// mattering (below 2^-54 x; at most 200 steps): the root for a > 1.
+__device__ __forceinline__ double newton_converge(double x, double a, const StepCoef &c)
+{
+    for (int k = 0; k < 200; ++k) {
         const double x2 = x * x;
         const double p = fma(c.h, fma(x, x2, -x), x - a);
         const double dp = fma(c.h3, x2, c.omh);
-        x = fma(-p, approx_rcp(dp), x);
+        const double step = p / dp;
+        x -= step;
+        if (!(fabs(step) > 0x1p-54 * x)) break;
     }
-    if (a > 1.0) {
-        for (int k = 0; k < 200; ++k) {
-            const double x2 = x * x;
-            const double p = fma(c.h, fma(x, x2, -x), x - a);
-            const double dp = fma(c.h3, x2, c.omh);
-            const double step = p / dp;
-            x -= step;
-            if (!(fabs(step) > 0x1p-54 * x)) break;
-        }
-    }
+    return x;
+}
+
+// (With the step count known only at run time, a lane with a > 1 selects
+// the start a and goes on after the common steps, in less code than the
+// restart of cubic_root_n for kernels that inline many roots; the
+// arithmetic is the same.)
+__device__ __forceinline__ double cubic_root(double xi, const StepCoef &c)
+{
+    const double a = fabs(xi);
+    double x = a > 1.0 ? a : root_start(a, c);
+    for (int k = 0; k < c.nit; ++k) x = newton_step(x, a, c);
+    if (a > 1.0) x = newton_converge(x, a, c);
     return copysign(x, xi);
 }
 
@@ -103,21 +130,12 @@ __device__ __forceinline__ double cubic_root_n(double xi, const StepCoef &c)
     const double a = fabs(xi);
     double x = root_start_t<(RV >= 4)>(a, c);
 #pragma unroll
-    for (int k = 0; k < NIT; ++k) {
-        const double x2 = x * x;
-        const double p = fma(c.h, fma(x, x2, -x), x - a);
-        const double dp = fma(c.h3, x2, c.omh);
-        x = fma(-p, approx_rcp(dp), x);
-    }
-    if (a > 1.0) {
-        for (int k = 0; k < 200; ++k) {
-            const double x2 = x * x;
-            const double p = fma(c.h, fma(x, x2, -x), x - a);
-            const double dp = fma(c.h3, x2, c.omh);
-            const double step = p / dp;
-            x -= step;
-            if (!(fabs(step) > 0x1p-54 * x)) break;
-        }
+    for (int k = 0; k < NIT; ++k) x = newton_step(x, a, c);
+    if (a > 1.0) {  // start again from a (this lane's first pass is discarded)
+        x = a;
+#pragma unroll
+        for (int k = 0; k < NIT; ++k) x = newton_step(x, a, c);
+        x = newton_converge(x, a, c);
     }
     return copysign(x, xi);
 }

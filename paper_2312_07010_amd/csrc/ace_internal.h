@@ -11,13 +11,15 @@ enum { BC_HN = 0, BC_HD = 1, BC_P = 2 };
 // Per-problem coefficients of one step (Sec. 2): kappa = eps^2 dt/dx^2,
 // h = dt/2, omh = 1 - h, oph = 1 + h, h3 = 3 h (the cubic's derivative is
 // 1 - h + 3 h theta^2), nit = Newton steps for |xi| <= 1, start2 = 1 when
-// the root iteration starts from its second-order expansion in h.
+// the root iteration starts from its second-order expansion in h, hs = the h
+// of that expansion (h, or 0 when h > 1/2: the start is then |xi| itself).
 struct StepCoef {
     double kappa;
     double h;
     double omh;
     double oph;
     double h3;
+    double hs;
     int nit;
     int start2;
     int fex;    // 1: the fully explicit comparison scheme (no cubic solve)

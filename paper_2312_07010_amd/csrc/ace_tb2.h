@@ -164,9 +164,11 @@ struct Region {
         auto level = [&](int k, auto FULLc, auto STOREc) __attribute__((always_inline)) {
             constexpr bool FULL = decltype(FULLc)::value, STORE = decltype(STOREc)::value;
             const int rd = (k - 1) & 1;
-            double eT = 0.0, eB = 0.0;
-            if (tr > 0) eT = eb(rd, 1, tr - 1)[tx];
-            if (tr < TRW - 1) eB = eb(rd, 0, tr + 1)[tx];
+            // (region rows 0 and RH-1 are never computed, so wavefront 0
+            // never uses eT nor wavefront TRW-1 eB: they read their own
+            // edge rows instead, in bounds and unused)
+            const double eT = eb(rd, 1, tr > 0 ? tr - 1 : 0)[tx];
+            const double eB = eb(rd, 0, tr < TRW - 1 ? tr + 1 : TRW - 1)[tx];
             double *__restrict__ lout = out + (LEVELS ? (int64_t)(k - 1) * level_stride : 0);
             double nv[RYT];
 #pragma unroll
@@ -231,7 +233,7 @@ __global__ __launch_bounds__(RX * TRW) void k_tb2(Shape s, StepCoef c, const dou
     g.load(s, in, v);
     MonAcc m;
     mon_zero(m);
-    g.template advance<MON, LEVELS, RV>(s, c, v, out, level_stride, EB, m);
+    g.template advance<MON, LEVELS, RV>(s, coef_vgpr(c), v, out, level_stride, EB, m);
     if (MON) block_reduce_store(m, red, partials + 3 * blockIdx.x);
 }
 

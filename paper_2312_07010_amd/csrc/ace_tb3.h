@@ -120,10 +120,11 @@ struct Geom {
 
 template <int BC, bool MON, int RV, int K, int TRW, int RYT, int OCC>
 __global__ __launch_bounds__(RX * TRW) __attribute__((amdgpu_waves_per_eu(OCC))) void k_tb3(
-    Shape s, StepCoef c, const double *__restrict__ in, double *__restrict__ out,
+    Shape s, StepCoef c0, const double *__restrict__ in, double *__restrict__ out,
     double *__restrict__ partials, int tiles_x, int tiles_y, int zchunk)
 {
     using G = Geom<K, TRW, RYT>;
+    const StepCoef c = coef_vgpr(c0);
     constexpr int NT = G::NT, RH = G::RH, OX = G::OX, OY = G::OY;
     __shared__ double EB[K * 2 * 2 * TRW * RX];  // [level][parity][top|bottom][wavefront][lane]
     __shared__ double red[3 * (NT / 64)];
@@ -245,11 +246,12 @@ __global__ __launch_bounds__(RX * TRW) __attribute__((amdgpu_waves_per_eu(OCC)))
                 xm[r] = lane_shift<0x138>(cq[r]);
                 xp[r] = lane_shift<0x130>(cq[r]);
             }
-            // i1 neighbours across wavefronts (rows of region row 0 and RH-1
-            // are never computed, so wavefronts 0 and TRW-1 skip them)
-            double eT = 0.0, eB = 0.0;
-            if (tr > 0) eT = eb(J - 1, rd, 1, tr - 1)[tx];
-            if (tr < TRW - 1) eB = eb(J - 1, rd, 0, tr + 1)[tx];
+            // i1 neighbours across wavefronts.  Region rows 0 and RH-1 are
+            // never computed, so wavefront 0 never uses eT nor wavefront
+            // TRW-1 eB: they read their own edge rows instead (in bounds,
+            // unused), which spares a branch and a zero per level.
+            const double eT = eb(J - 1, rd, 1, tr > 0 ? tr - 1 : 0)[tx];
+            const double eB = eb(J - 1, rd, 0, tr < TRW - 1 ? tr + 1 : TRW - 1)[tx];
             const bool mon_plane = MON && J == 1 && zo >= z0 && zo < z1;
             // buffer over output plane zo (used at J == K only): rows at
             // offset kNoStore fall outside it and are not written
