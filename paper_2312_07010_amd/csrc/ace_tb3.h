@@ -7,8 +7,11 @@
 // recomputed instead of exchanged) and marches along i0.  Lane x of
 // wavefront w holds the RYT consecutive region rows w RYT .. w RYT + RYT - 1
 // of column x in registers, for every time level, in register queues along
-// i0 (level 0: planes zc-1 .. zc+2; level j = 1..K-1: the three planes that
-// level j+1 needs next).  At march position zc it computes level j of plane
+// i0 (level 0: planes zc-1 .. zc+1, the slot of zc-1 reloaded with plane
+// zc+2 as soon as level 1 has read it, about two thirds of a position ahead
+// of its use; level j = 1..K-1: the three planes that level j+1 needs
+// next).  All queues have three slots, so three march positions fix every
+// slot at compile time.  At march position zc it computes level j of plane
 // zc - j + 1 for j = 1..K; level K is the output.  Of the seven neighbours of
 // a node:
 //   * i0: from the level's register queue;
@@ -200,16 +203,15 @@ __global__ __launch_bounds__(RX * TRW) __attribute__((amdgpu_waves_per_eu(OCC)))
         const int64_t zs = z0 - K + 1;           // first march position
         const int64_t zend = z1 + K - 2;         // last march position
         const int64_t zlast = z1 + K - 1;        // last level-0 plane needed
-        double q0[4][RYT];
+        double q0[3][RYT];
         double qj[G::NQ][3][RYT];
         {
-            const int64_t b0 = base(zs - 1), b1 = base(zs), b2 = base(zs + 1), b3 = base(zs + 2);
+            const int64_t b0 = base(zs - 1), b1 = base(zs), b2 = base(zs + 1);
 #pragma unroll
             for (int r = 0; r < RYT; ++r) {
                 q0[0][r] = ld(b0, off[r]);
                 q0[1][r] = ld(b1, off[r]);
                 q0[2][r] = ld(b2, off[r]);
-                q0[3][r] = ld(b3, off[r]);
             }
         }
 #pragma unroll
@@ -222,7 +224,7 @@ __global__ __launch_bounds__(RX * TRW) __attribute__((amdgpu_waves_per_eu(OCC)))
         // zc - K + 1 (level K's plane)
         static_assert(K >= 2, "the cursor starts at the last plane loaded above");
         PlaneCursor<BC> cur;
-        cur.init(zs + 2, s.M0, PS);
+        cur.init(zs + 1, s.M0, PS);
         int64_t ooff = (zs - K + 1) * PS;
         // edges of level-0 plane zs, read at the first position
         eb(0, (int)((zs - 1) & 1), 0, tr)[tx] = q0[1][0];
@@ -300,20 +302,19 @@ __global__ __launch_bounds__(RX * TRW) __attribute__((amdgpu_waves_per_eu(OCC)))
         };
 
         // One march position with the queue slots fixed at compile time:
-        // level 0 planes zc-1 .. zc+2 in q0[S % 4 ..], level j planes
+        // level 0 planes zc-1, zc, zc+1 in q0[S % 3 ..], level j planes
         // zc-j-1, zc-j, zc-j+1 in qj[j-1][S % 3 ..] (the last written here).
         auto body = [&](auto SS) __attribute__((always_inline)) -> bool {
             constexpr int S = decltype(SS)::value;
-            constexpr int A0 = S % 4, B0 = (S + 1) % 4, C0 = (S + 2) % 4;
             constexpr int P0 = S % 3, P1 = (S + 1) % 3, P2 = (S + 2) % 3;
             // level 1 of plane zc
-            level(std::integral_constant<int, 1>(), q0[A0], q0[B0], q0[C0], qj[0][P2]);
+            level(std::integral_constant<int, 1>(), q0[P0], q0[P1], q0[P2], qj[0][P2]);
             // next level-0 plane into the slot level 1 just freed
             {
-                if (zc + 3 <= zlast) cur.next(s.M0, PS);  // plane min(zc + 3, zlast)
+                if (zc + 2 <= zlast) cur.next(s.M0, PS);  // plane min(zc + 2, zlast)
                 const int64_t bn = cur.off;
 #pragma unroll
-                for (int r = 0; r < RYT; ++r) q0[A0][r] = ld(bn, off[r]);
+                for (int r = 0; r < RYT; ++r) q0[P0][r] = ld(bn, off[r]);
             }
             // levels 2..K, each from the one below (active once its inputs exist)
             if constexpr (K >= 2) {
@@ -332,8 +333,8 @@ __global__ __launch_bounds__(RX * TRW) __attribute__((amdgpu_waves_per_eu(OCC)))
             }
             if (zc >= zend) return true;
             // edges of level-0 plane zc+1 for the next position
-            eb(0, (int)(zc & 1), 0, tr)[tx] = q0[C0][0];
-            eb(0, (int)(zc & 1), 1, tr)[tx] = q0[C0][RYT - 1];
+            eb(0, (int)(zc & 1), 0, tr)[tx] = q0[P2][0];
+            eb(0, (int)(zc & 1), 1, tr)[tx] = q0[P2][RYT - 1];
             __syncthreads();
             ++zc;
             ooff += PS;
@@ -343,15 +344,6 @@ __global__ __launch_bounds__(RX * TRW) __attribute__((amdgpu_waves_per_eu(OCC)))
             if (body(std::integral_constant<int, 0>())) break;
             if (body(std::integral_constant<int, 1>())) break;
             if (body(std::integral_constant<int, 2>())) break;
-            if (body(std::integral_constant<int, 3>())) break;
-            if (body(std::integral_constant<int, 4>())) break;
-            if (body(std::integral_constant<int, 5>())) break;
-            if (body(std::integral_constant<int, 6>())) break;
-            if (body(std::integral_constant<int, 7>())) break;
-            if (body(std::integral_constant<int, 8>())) break;
-            if (body(std::integral_constant<int, 9>())) break;
-            if (body(std::integral_constant<int, 10>())) break;
-            if (body(std::integral_constant<int, 11>())) break;
         }
         __syncthreads();  // every wavefront is done with the edge buffers of this segment
     }
