@@ -259,10 +259,14 @@ __global__ __launch_bounds__(RX * TRW) __attribute__((amdgpu_waves_per_eu(OCC)))
             // offset kNoStore fall outside it and are not written
             const __amdgpu_buffer_rsrc_t orsrc =
                 __builtin_amdgcn_make_buffer_rsrc(out + (J == K ? ooff : 0), (short)0, (int)(PS * 8), kBufWord3);
+            // Every row is computed, also the ring rows ry < J and
+            // ry >= RH - J, whose values at this level are wrong: they only
+            // reach ring rows of the next level and rows that are neither
+            // stored nor monitored (oof is kNoStore there), and skipping them
+            // would cost a test per row in every wavefront to spare work in
+            // the two edge wavefronts, which otherwise wait at the barrier.
 #pragma unroll
             for (int r = 0; r < RYT; ++r) {
-                const int ry = tr * RYT + r;
-                if (ry < J || ry >= RH - J) continue;  // wave-uniform
                 const double p = cq[r];
                 double zm = zmq[r], zp = zpq[r];
                 double ym = (r > 0) ? cq[r > 0 ? r - 1 : 0] : eT;
