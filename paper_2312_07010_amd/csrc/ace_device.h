@@ -118,26 +118,61 @@ __device__ __forceinline__ double cubic_root(double xi, const StepCoef &c)
     return copysign(x, xi);
 }
 
-// Same root with the start and the Newton count fixed at compile time
-// (RV > 0, see root_variant; the iteration and hence every rounding is
-// identical to cubic_root with the matching coefficients), so the loop
-// unrolls and its constants stay in registers.
+// The root's two paths for a = |xi| with the start and the Newton count
+// fixed at compile time (RV > 0, see root_variant): root_common is the start
+// and NIT steps, the root for a <= 1; root_restart the root for a > 1 (from
+// a, the same NIT steps, then newton_converge).  The iteration and hence
+// every rounding is identical to cubic_root's with the matching
+// coefficients, so the loop unrolls and its constants stay in registers.
+template <int RV>
+__device__ __forceinline__ double root_common(double a, const StepCoef &c)
+{
+    constexpr int NIT = RV > 0 ? (RV & 3) : 1;
+    double x = root_start_t<(RV >= 4)>(a, c);
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) x = newton_step(x, a, c);
+    return x;
+}
+
+template <int RV>
+__device__ __forceinline__ double root_restart(double a, const StepCoef &c)
+{
+    constexpr int NIT = RV > 0 ? (RV & 3) : 1;
+    double x = a;
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) x = newton_step(x, a, c);
+    return newton_converge(x, a, c);
+}
+
 template <int RV>
 __device__ __forceinline__ double cubic_root_n(double xi, const StepCoef &c)
 {
     if (RV <= 0) return cubic_root(xi, c);
-    constexpr int NIT = RV > 0 ? (RV & 3) : 1;
     const double a = fabs(xi);
-    double x = root_start_t<(RV >= 4)>(a, c);
-#pragma unroll
-    for (int k = 0; k < NIT; ++k) x = newton_step(x, a, c);
-    if (a > 1.0) {  // start again from a (this lane's first pass is discarded)
-        x = a;
-#pragma unroll
-        for (int k = 0; k < NIT; ++k) x = newton_step(x, a, c);
-        x = newton_converge(x, a, c);
-    }
+    double x = root_common<RV>(a, c);
+    if (a > 1.0) x = root_restart<RV>(a, c);  // this lane's first pass is discarded
     return copysign(x, xi);
+}
+
+// The roots of N values with one test for the a > 1 case (on the largest
+// |xi|; a NaN never needs it), so the common paths of the N values form one
+// block that the compiler can interleave.  Same results as cubic_root_n.
+template <int RV, int N>
+__device__ __forceinline__ void cubic_roots_n(const double (&xi)[N], double (&th)[N], const StepCoef &c)
+{
+    double amax = fabs(xi[0]);
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        th[r] = root_common<RV>(fabs(xi[r]), c);
+        if (r > 0) amax = fmax(amax, fabs(xi[r]));
+    }
+    if (amax > 1.0) {
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+            if (fabs(xi[r]) > 1.0) th[r] = root_restart<RV>(fabs(xi[r]), c);
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r) th[r] = copysign(th[r], xi[r]);
 }
 
 // Explicit part xi from the node value p and the sum over axes of its two

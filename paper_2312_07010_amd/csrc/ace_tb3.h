@@ -265,6 +265,7 @@ __global__ __launch_bounds__(RX * TRW) __attribute__((amdgpu_waves_per_eu(OCC)))
             // stored nor monitored (oof is kNoStore there), and skipping them
             // would cost a test per row in every wavefront to spare work in
             // the two edge wavefronts, which otherwise wait at the barrier.
+            double xi[RYT], th[RYT];  // (compiled root variants: all rows' roots at once)
 #pragma unroll
             for (int r = 0; r < RYT; ++r) {
                 const double p = cq[r];
@@ -282,9 +283,13 @@ __global__ __launch_bounds__(RX * TRW) __attribute__((amdgpu_waves_per_eu(OCC)))
                     if (xb1) xpv = wall;
                 }
                 const double nsum = ((zm + zp) + (ym + yp)) + (xmv + xpv);
-                const double v = update_n<3, RV>(p, nsum, c);
-                if (J < K) dst[r] = v;
-                else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(BufB64, v), orsrc, (int)oof[r], 0, 0);
+                if constexpr (RV > 0) {
+                    xi[r] = explicit_part<3>(p, nsum, c);
+                } else {
+                    const double v = update_n<3, RV>(p, nsum, c);
+                    if (J < K) dst[r] = v;
+                    else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(BufB64, v), orsrc, (int)oof[r], 0, 0);
+                }
                 if (mon_plane && oof[r] != kNoStore) {
                     const double dz = zp - p, dy = yp - p, dx = xpv - p;
                     double g = fma(dz, dz, fma(dy, dy, dx * dx));
@@ -296,6 +301,14 @@ __global__ __launch_bounds__(RX * TRW) __attribute__((amdgpu_waves_per_eu(OCC)))
                     m.bulk += bulk_term(p);
                     m.grad += g;
                     m.mx = nan_max(m.mx, fabs(p));
+                }
+            }
+            if constexpr (RV > 0) {
+                cubic_roots_n<RV>(xi, th, c);
+#pragma unroll
+                for (int r = 0; r < RYT; ++r) {
+                    if (J < K) dst[r] = th[r];
+                    else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(BufB64, th[r]), orsrc, (int)oof[r], 0, 0);
                 }
             }
             if (J < K) {
