@@ -170,7 +170,10 @@ struct Region {
             const double eT = eb(rd, 1, tr > 0 ? tr - 1 : 0)[tx];
             const double eB = eb(rd, 0, tr < TRW - 1 ? tr + 1 : TRW - 1)[tx];
             double *__restrict__ lout = out + (LEVELS ? (int64_t)(k - 1) * level_stride : 0);
-            double nv[RYT];
+            // (FULL with a compiled root variant: every row's xi first, then
+            // all rows' roots together)
+            constexpr bool JOINT = FULL && RV > 0;
+            double nv[RYT], xi[RYT];
 #pragma unroll
             for (int r = 0; r < RYT; ++r) {
                 nv[r] = v[r];
@@ -196,9 +199,19 @@ struct Region {
                     m.mx = nan_max(m.mx, fabs(p));
                 }
                 const double nsum = (ym + yp) + (xm + xp);
-                const double val = update_n<2, RV>(p, nsum, c);
-                nv[r] = val;
-                if (STORE && oof[r] >= 0) lout[oof[r]] = val;
+                if constexpr (JOINT) {
+                    xi[r] = explicit_part<2>(p, nsum, c);
+                } else {
+                    const double val = update_n<2, RV>(p, nsum, c);
+                    nv[r] = val;
+                    if (STORE && oof[r] >= 0) lout[oof[r]] = val;
+                }
+            }
+            if constexpr (JOINT) {
+                cubic_roots_n<RV>(xi, nv, c);
+#pragma unroll
+                for (int r = 0; r < RYT; ++r)
+                    if (STORE && oof[r] >= 0) lout[oof[r]] = nv[r];
             }
 #pragma unroll
             for (int r = 0; r < RYT; ++r) v[r] = nv[r];
