@@ -159,6 +159,34 @@ def test_register_regions_do_not_change_results(ace):
     b.close()
 
 
+def test_register_regions_with_values_beyond_one(ace):
+    """Large 2D instances (several dt, hence root variants) with initial values
+    up to 1.6 in magnitude, so that |xi| > 1 at many nodes and the root starts
+    again from |xi| (once per level for all rows of a full wavefront), over
+    register regions of 32 and 64 rows at depths 1 and 5: every instance bit
+    for bit as its own single-instance run."""
+    insts = [x for x in _mixed(5) if x[0] == 2 and x[1][0] >= 89]
+    b = ace.Batch(insts)
+    rng = np.random.default_rng(12)
+    phi0 = [rng.uniform(-1.6, 1.6, shp) for shp in b.shapes]
+    refs = []
+    for inst, x0 in zip(insts, phi0):
+        s = ace.Solver(*inst)
+        s.set_phi0(x0)
+        s.step(13)
+        refs.append(s.get_phi())
+        s.close()
+    for rows in (32, 64):
+        b.set_region(rows)
+        for depth in (1, 5):
+            b.set_depth(depth)
+            b.set_all(phi0)
+            b.step(13)
+            for i, (x, y) in enumerate(zip(b.get_all(), refs)):
+                assert np.array_equal(x, y), (rows, depth, insts[i])
+    b.close()
+
+
 def test_direct_launches_equal_graph_replays(ace):
     """ace_batch_set_graphs(0) issues the queue reset and the persistent
     launch directly; every instance ends bit for bit where the graph replay

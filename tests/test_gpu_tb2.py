@@ -65,6 +65,38 @@ def test_every_region_equals_the_one_step_kernel(ace, orc, bc, shape):
 
 
 @pytest.mark.parametrize("bc", [0, 1, 2])
+@pytest.mark.parametrize("dt", [2e-3, 0.2])
+def test_every_region_with_values_beyond_one(ace, orc, bc, dt):
+    """Initial values up to 1.6 in magnitude put |xi| > 1 at many nodes, where
+    the root starts again from |xi| and continues past its fixed Newton steps
+    (tested once per level for all rows of a wavefront whose rows are all
+    inside the level, per row elsewhere).  At both time steps (one Newton step
+    from the second-order start, and several) every region shape and depth
+    still equals the one-step kernel bit for bit, and the oracle."""
+    s, p = _rect(ace, orc, (100, 130), bc, dt=dt, kappa=0.15)
+    phi0 = np.random.default_rng(90 + bc + int(dt * 100)).uniform(-1.6, 1.6, p.shape)
+    want, Ew, _ = p.run(phi0, 9, 3)
+    s.set_kernel(ace.ACE_KERNEL_DIRECT)
+    s.set_phi0(phi0)
+    Ed, md = s.run_monitored(9, 3)
+    ref = s.get_phi()
+    assert np.abs(phi0).max() > 1.5
+    np.testing.assert_allclose(ref, want, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(Ed, Ew, rtol=1e-12)
+    for rows, rpt in VARIANTS:
+        kmax = rows // 2 - 4
+        for depth in sorted({1, 2, 5, kmax} & set(range(1, kmax + 1))):
+            s.set_kernel(ace.ACE_KERNEL_TBLOCK, min(depth, 12))
+            s.set_region2d(rows, rpt)
+            s.set_phi0(phi0)
+            E, m = s.run_monitored(9, 3)
+            assert np.array_equal(s.get_phi(), ref), (rows, rpt, depth)
+            assert np.array_equal(m, md), (rows, rpt, depth)
+            np.testing.assert_allclose(E, Ed, rtol=1e-13)
+    s.close()
+
+
+@pytest.mark.parametrize("bc", [0, 1, 2])
 def test_regions_leave_nan_margins_untouched(ace, orc, bc):
     import torch
     s, p = _rect(ace, orc, (131, 70), bc)
