@@ -22,10 +22,10 @@
 //   * i2: the neighbouring lanes' registers, moved by DPP lane shifts (no LDS
 //     round trip on the critical path; the lane at the region edge receives
 //     0, a ring node).
-// The LDS holds per level only two rows per wavefront.  Every value is
-// computed with exactly the arithmetic and
-// neighbour order of the one-step kernels, so K steps of this kernel equal K
-// one-step launches bit for bit.
+// The LDS holds per level only two rows per wavefront.  Every value that
+// reaches the output is computed with exactly the arithmetic and neighbour
+// order of the one-step kernels, so K steps of this kernel equal K one-step
+// launches bit for bit.
 //
 // Boundary conditions.  Level-0 values outside the domain are loaded
 // BC-mapped (clamped node for Neumann, 0 for Dirichlet, wrapped node for
@@ -248,10 +248,10 @@ __global__ __launch_bounds__(RX * TRW) __attribute__((amdgpu_waves_per_eu(OCC)))
                 xm[r] = lane_shift<0x138>(cq[r]);
                 xp[r] = lane_shift<0x130>(cq[r]);
             }
-            // i1 neighbours across wavefronts.  Region rows 0 and RH-1 are
-            // never computed, so wavefront 0 never uses eT nor wavefront
-            // TRW-1 eB: they read their own edge rows instead (in bounds,
-            // unused), which spares a branch and a zero per level.
+            // i1 neighbours across wavefronts.  Wavefront 0's eT and wavefront
+            // TRW-1's eB would lie outside the region: they read their own
+            // edge rows instead (in bounds, no branch).  The rows they feed,
+            // region rows 0 and RH-1, are ring rows at every level.
             const double eT = eb(J - 1, rd, 1, tr > 0 ? tr - 1 : 0)[tx];
             const double eB = eb(J - 1, rd, 0, tr < TRW - 1 ? tr + 1 : TRW - 1)[tx];
             const bool mon_plane = MON && J == 1 && zo >= z0 && zo < z1;
