@@ -198,37 +198,42 @@ def test_3d_periodic_512_monitors(ace, orc, inputs):
 @pytest.mark.parametrize("interior,n", [(16, 96), (64, 512)])
 def test_slab_share_matches_periodic_domain(ace, interior, n):
     """One GPU's share of a slab decomposition along axis 0: `interior`
-    planes plus 2 halo planes on each side, stepped two steps per launch,
-    the halos refreshed after every launch by device copies (standing in
-    for the exchange with the neighbouring GPUs; here the slab is its own
-    neighbour).  The interior then evolves bit for bit as the periodic
-    domain of the interior planes alone; (64, 512) is the real per-GPU
-    shape of the 512^3 workload on 8 GPUs."""
+    planes plus 3 halo planes on each side, stepped three steps between
+    exchanges, the halos refreshed after each interval by device copies
+    (standing in for the exchange with the neighbouring GPUs; here the slab
+    is its own neighbour).  The interior then evolves bit for bit as the
+    periodic domain of the interior planes alone, with the library's default
+    blocked kernel and with the two- and three-step register-region kernels;
+    (64, 512) is the real per-GPU shape of the 512^3 workload on 8 GPUs."""
     import torch
-    halo = 2
+    halo = 3
     P = interior + 2 * halo
     dx, dt, eps = 1.0 / n, 5e-4, 0.02
-    s = ace.Solver(3, [P, n, n], [0.0] * 3, [P * dx, 1.0, 1.0], eps, dt, "P")
-    s.use_torch_stream()
-    s.set_kernel(ace.ACE_KERNEL_TBLOCK)
-    a = torch.empty(P * n * n, dtype=torch.float64, device="cuda")
-    b = torch.empty_like(a)
-    s.bind_fields(a, b)
     x = np.random.default_rng(interior).uniform(-1, 1, (interior, n, n))
-    s.set_phi0(np.concatenate([x[-halo:], x, x[:halo]]))
     steps = 12
-    for _ in range(steps // 2):
-        s.step(2)
-        cur = a if s.field_ptr() == a.data_ptr() else b
-        v = cur.view(P, n, n)
-        v[:halo].copy_(v[interior:interior + halo])
-        v[halo + interior:].copy_(v[halo:2 * halo])
-    got = v[halo:halo + interior].cpu().numpy()
     ref = ace.Solver(3, [interior, n, n], [0.0] * 3, [interior * dx, 1.0, 1.0], eps, dt, "P")
     ref.set_phi0(x)
     ref.step(steps)
-    assert np.array_equal(got, ref.get_phi())
+    want = ref.get_phi()
     ref.close()
+    s = ace.Solver(3, [P, n, n], [0.0] * 3, [P * dx, 1.0, 1.0], eps, dt, "P")
+    s.use_torch_stream()
+    a = torch.empty(P * n * n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    s.bind_fields(a, b)
+    for region in (None, (2, 32, 4), (3, 48, 3)):
+        s.set_kernel(ace.ACE_KERNEL_TBLOCK)
+        if region:
+            s.set_region3d(*region)
+        s.set_phi0(np.concatenate([x[-halo:], x, x[:halo]]))
+        for _ in range(steps // halo):
+            s.step(halo)
+            cur = a if s.field_ptr() == a.data_ptr() else b
+            v = cur.view(P, n, n)
+            v[:halo].copy_(v[interior:interior + halo])
+            v[halo + interior:].copy_(v[halo:2 * halo])
+        got = v[halo:halo + interior].cpu().numpy()
+        assert np.array_equal(got, want), region
     s.close()
 
 
