@@ -1070,10 +1070,13 @@ int ace_autotune(ace_solver *s, int64_t trial_steps, char *json, size_t cap)
     if (s->p.d == 3 && tblock_supported(s->shape))
         for (int zc : {0, 16, 24, 32, 40, 48, 64, 128})  // 0: persistent grid
             if (zc <= std::max<int64_t>(s->shape.M0, 16)) cands.push_back({ACE_KERNEL_TBLOCK, zc, k0, -1, v20});
-    // the configurable 3D kernel: every depth and region shape, fewer plane chunks
+    // the configurable 3D kernel: every depth and region shape, fewer plane
+    // chunks.  Long chunks matter when a chunk count leaves the last round of
+    // one-workgroup-per-CU launches half empty (512^3 at depth 3: 117 tiles x
+    // 8 chunks of 64 = 936 workgroups on 256 CUs, against 234 of 256 planes).
     if (s->p.d == 3 && tb3_supported(s->shape))
         for (int v = 0; v < TB3_VARIANTS; ++v)
-            for (int zc : {0, 16, 32, 64})
+            for (int zc : {0, 16, 32, 64, 128, 256})
                 if (zc <= std::max<int64_t>(s->shape.M0, 16)) cands.push_back({ACE_KERNEL_TBLOCK, zc, k0, v, v20});
     if (s->p.d == 2 && tblock2d_supported(s->shape)) {
         for (int k2 : {1, 2, 3, 4, 5, 6, 8, 10, 12})

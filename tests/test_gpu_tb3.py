@@ -49,7 +49,7 @@ def test_every_variant_equals_the_one_step_kernel(ace, orc, bc, N):
     s.step(29)
     ref29 = s.get_phi()
     for v in VARIANTS:
-        for planes in (0, 8, 13, 40):
+        for planes in (0, 8, 13, 40, 256):
             s.set_kernel(ace.ACE_KERNEL_TBLOCK)
             s.set_region3d(*v)
             assert s.get_region3d() == v

@@ -122,12 +122,20 @@ def _subbox_oracle(orc, w, phi0, centre, T, kappa, h, scheme=0):
 
 
 @pytest.mark.timeout(600)
-def test_3d_periodic_512_sampled(ace, orc, inputs):
+@pytest.mark.parametrize("config", ["default", (3, 48, 3, 256), (3, 48, 4, 128)])
+def test_3d_periodic_512_sampled(ace, orc, inputs, config):
+    """Sampled nodes of the benchmark field after 1 and 20 steps, on the
+    default kernel and on register regions with long plane chunks (the
+    autotuner's candidates that fill one or two rounds of workgroups)."""
     w = inputs.W3D
     s = ace.Solver(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
     p = orc.Problem(w.d, w.N, w.L, w.R, w.eps, w.dt, w.bc)
     assert s.shape == (512, 512, 512) and p.shape == s.shape
     assert s.params["kappa"] == p.kappa
+    if config != "default":
+        s.set_kernel(ace.ACE_KERNEL_TBLOCK)
+        s.set_region3d(*config[:3])
+        s.set_plane_chunk(config[3])
     phi0 = w_field(w, s)
     rng = np.random.default_rng(5)
     # samples: random nodes, the periodic seams and corners, the sphere's surface
@@ -144,7 +152,7 @@ def test_3d_periodic_512_sampled(ace, orc, inputs):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("config", ["default", "auto", (3, 48, 3, 64), (2, 32, 4, 32)])
+@pytest.mark.parametrize("config", ["default", "auto", (3, 48, 3, 64), (3, 48, 3, 256), (2, 32, 4, 32)])
 def test_3d_periodic_512_fex_sampled(ace, orc, inputs, config):
     """The fully explicit comparison scheme on the benchmark field (its extra
     line in the benchmark, which runs on the autotuned launch), on the
