@@ -374,6 +374,46 @@ def test_root_across_time_steps(ace, orc, d, bc, N, dt):
     np.testing.assert_allclose(s.get_phi(), p.run(phi0, 20)[0], rtol=0, atol=2e-14)
 
 
+@pytest.mark.parametrize("dt", [1.2, 1.5])
+@pytest.mark.parametrize("d,bc,N", [(1, 2, 64), (2, 0, 33), (3, 1, 12), (3, 2, 30)])
+def test_root_beyond_half_unit_h(ace, orc, d, bc, N, dt):
+    """h = dt/2 > 1/2 (outside Theorem 2's conditions; the root is still
+    unique for dt < 2, Remark 1): the root starts from |xi| itself (the
+    expansion's coefficient is 0 there) and takes the host's Newton count,
+    and the few nodes the field carries past 1 take the restart.  Every
+    kernel, the 3D register regions included, gives the same field bit for
+    bit and matches the oracle.  Near theta = 0 the root amplifies a
+    difference in xi by 1/(1 - h) per step, so the oracle tolerances carry
+    that factor."""
+    kappa = 0.02 / d
+    h = dt / 2
+    s, p = _pair(ace, orc, d, N, bc, kappa=kappa, dt=dt)
+    assert s.status == ace.ACE_W_CONDITIONS
+    phi0 = np.random.default_rng(int(dt * 10) + 3 * d + bc).uniform(-1, 1, p.shape)
+    want1 = p.step(phi0)
+    want5 = p.run(phi0, 5)[0]
+    assert np.abs(want5).max() > 1.0  # the restart path runs
+    kernels = [(ace.ACE_KERNEL_DIRECT, None)]
+    kernels += [(ace.ACE_KERNEL_RESIDENT, None)] if d == 1 else [(ace.ACE_KERNEL_TBLOCK, None)]
+    if d == 3:
+        kernels += [(ace.ACE_KERNEL_TBLOCK, (3, 48, 3)), (ace.ACE_KERNEL_TBLOCK, (2, 32, 4))]
+    ref = None
+    for k, region in kernels:
+        s.set_kernel(k)
+        if region:
+            s.set_region3d(*region)
+        s.set_phi0(phi0)
+        s.step(1)
+        np.testing.assert_allclose(s.get_phi(), want1, rtol=0, atol=2e-15 / (1 - h))
+        s.step(4)
+        got = s.get_phi()
+        np.testing.assert_allclose(got, want5, rtol=0, atol=1e-15 / (1 - h) ** 5)
+        if ref is None:
+            ref = got
+        assert np.array_equal(got, ref), (k, region)
+    s.close()
+
+
 @pytest.mark.parametrize("bc", [0, 1, 2])
 def test_3d_ragged_box_all_kernels(ace, orc, bc):
     """A box with equal spacing but different extents, so every tile dimension
